@@ -1,0 +1,283 @@
+/*
+ * wh.h -- C ABI of the MI355X WaveHoltz library.
+ *
+ * WaveHoltz (Appelo, Banks, Henshaw, Schwendeman, "An optimal O(N) Helmholtz
+ * solver for complex geometry using WaveHoltz and overset grids") finds the
+ * solution u of the discrete Helmholtz problem
+ *
+ *     c^2(x) Delta_{h,p} u + omega^2 u = f   on the interior nodes,   u = 0 on the walls
+ *
+ * (Sec. 2.1, eq. HelmholtzBVP with L = c^2 Delta and homogeneous Dirichlet
+ * data) by filtering time-periodic solutions of the forced wave equation
+ * w_tt = c^2 Delta_h w - f cos(omega t) (Sec. 2.1, eq. waveEquation).
+ * This library implements the explicit, single-Cartesian-grid form:
+ *   - the explicit leapfrog scheme with the frequency correction of
+ *     Appendix A.1 (Sec. 4.2.1, eq. WaveSchemeexplicit),
+ *   - the trapezoid time filter with the adjusted parameter alpha_d
+ *     (Sec. 4.2.1, eqs. updateDiscreteExplicit and alphad), fused into the
+ *     time steps,
+ *   - the fixed-point iteration of Alg. 1 and restarted GMRES on the linear
+ *     form (I - S_h) v = b of Sec. 5.3.
+ *
+ * Conventions
+ *   Grid      The unit box [0,1]^dim, dim = 2 or 3, with n[m] >= 2 cells per
+ *             axis (spacing 1/n[m]).  Order p = 2 (5/7-point) or p = 4
+ *             (the b_0 + b_1 expansion of Sec. 6.1, i.e. the 9/13-point star);
+ *             for p = 4 ghost values beyond a wall are the odd reflection
+ *             u(-j) = -u(j).
+ *   Arrays    Every grid function crossing this ABI is a dense array of
+ *             (n_z+1)(n_y+1)(n_x+1) (or (n_y+1)(n_x+1)) doubles, x fastest,
+ *             holding all nodes including the walls.  Values given on wall
+ *             nodes are ignored; outputs hold exactly 0 there.
+ *   Memory    Pointers documented as "device" must be device memory of the
+ *             context's device (e.g. a torch tensor's data_ptr()).  "host or
+ *             device" pointers are told apart by the on_device flag.  The
+ *             caller owns every buffer; the library keeps no caller pointer
+ *             after a call returns, except the workspace, which the caller
+ *             binds once and must keep alive (and unused by anyone else)
+ *             until the context is destroyed or rebound.
+ *   Streams   All device work is enqueued on the stream given to wh_create
+ *             (NULL = the null stream).  Calls returning host scalars
+ *             (wh_solve, wh_dot-style diagnostics) synchronise that stream;
+ *             wh_apply, wh_apply_A and wh_run_periods do not.
+ *   Errors    Every call returns a wh_status; 0 is success.  Arguments are
+ *             validated before any device work is enqueued.  wh_last_error
+ *             returns a message for the most recent failure on a context.
+ *             No C++ exception crosses this boundary.
+ *   Threads   A context is not thread safe; distinct contexts are
+ *             independent.  Calls that overlap on one context race.
+ */
+#ifndef WH_H
+#define WH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define WH_API __attribute__((visibility("default")))
+#else
+#define WH_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wh_ctx wh_ctx;
+
+typedef enum {
+  WH_OK = 0,
+  WH_EINVAL = -1,     /* bad argument (shape, pointer, range) */
+  WH_ENOMEM = -2,     /* workspace missing or too small */
+  WH_EDEVICE = -3,    /* a HIP runtime call failed */
+  WH_EUNSTABLE = -4,  /* requested time step violates the explicit stability limit */
+  WH_ENOTCONV = -5,   /* solver stopped at maxit without reaching rtol */
+  WH_ENONFINITE = -6, /* a residual norm became NaN or Inf */
+  WH_ESTATE = -7      /* call made before the setters it depends on */
+} wh_status;
+
+/* Precision of the wave state and stencil arithmetic.  The filter
+ * accumulator, the weights and everything in the outer solvers stay FP64. */
+typedef enum { WH_FP64 = 0, WH_FP32_STATE = 1 } wh_precision;
+
+typedef enum { WH_SOLVER_FPI = 0, WH_SOLVER_GMRES = 1 } wh_solver;
+
+/* Time parameters of one WaveHoltz application (explicit correction recipe,
+ * Appendix A.1; stability limit of Sec. 3.2, eq. dtForCartesian):
+ *   nt       time steps per corrected period,
+ *   periods  Np, periods per application (filter length Tbar = Np * nt * dt),
+ *   dt       (2/omega) sin(pi/nt),
+ *   omega    the Helmholtz frequency,
+ *   omega_e  corrected forcing frequency 2 pi / (nt dt),
+ *   alpha    filter parameter used (alpha_d = tan(pi/nt)/tan(2pi/nt) unless overridden),
+ *   cfl      c_max dt sqrt(sum_m n_m^2), the CFL number (stable iff <= C_{2,p},
+ *            C_{2,2} = 1, C_{2,4} = sqrt(3)/2),
+ *   c2max    maximum of c^2 over interior nodes. */
+typedef struct {
+  int32_t nt;
+  int32_t periods;
+  double dt;
+  double omega;
+  double omega_e;
+  double alpha;
+  double cfl;
+  double c2max;
+} wh_time_params;
+
+/* Iteration callback: k = 1-based iteration (applies for FPI, Arnoldi steps
+ * for GMRES), rel_res = residual estimate relative to ||b||_2. */
+typedef void (*wh_iter_callback)(int32_t k, double rel_res, void *user);
+
+typedef struct {
+  int32_t method;   /* wh_solver */
+  int32_t restart;  /* GMRES restart length m (1..WH_MAX_RESTART); ignored by FPI */
+  int32_t maxit;    /* maximum applies (FPI) or Arnoldi steps (GMRES) */
+  int32_t flags;    /* reserved, must be 0 */
+  double rtol;      /* stop when ||b - A v||_2 <= rtol ||b||_2; 0 = run maxit (FPI) */
+  wh_iter_callback on_iter; /* nullable */
+  void *user;
+} wh_solve_opts;
+
+/* Results of wh_solve.  For FPI the residual of iterate k is v^k - v^{k-1}
+ * (= b - A v^{k-1}); for GMRES it is the true residual b - A v at exit.
+ *   iters       FPI applies or GMRES Arnoldi steps performed
+ *   applies     WaveHoltz applications performed (includes b and restarts)
+ *   rel_res     ||r||_2 / ||b||_2 at exit
+ *   scaled_res  ||r||_2 / sqrt(number of nodes) (the paper's scaled norm, Sec. 7)
+ *   cr_last     last residual ratio ||r^k|| / ||r^{k-1}|| (FPI) or the
+ *               average per-step reduction (GMRES)
+ *   cr_avg      (||r^k|| / ||r^1||)^{1/(k-1)}, average convergence rate
+ *   ecr         cr_avg^{1/periods}, the effective rate of Sec. 7
+ *   mu_pred     predicted FPI rate max |beta_d(lambda~)| (Theorem 2) for
+ *               constant c^2; NaN when c^2 varies
+ *   seconds     wall time of the call
+ *   bnorm       ||b||_2 with b = W_h(0, f)
+ *   point_steps interior-node time steps executed */
+typedef struct {
+  int32_t iters;
+  int32_t applies;
+  double rel_res;
+  double scaled_res;
+  double cr_last;
+  double cr_avg;
+  double ecr;
+  double mu_pred;
+  double seconds;
+  double bnorm;
+  double point_steps;
+} wh_solve_info;
+
+#define WH_MAX_RESTART 256
+
+/* Version of the ABI (major * 10000 + minor * 100 + patch). */
+WH_API int32_t wh_version(void);
+
+/* Human-readable name of a status code (static string). */
+WH_API const char *wh_status_string(int32_t status);
+
+/* Pure host computation of the time parameters (no device needed): the
+ * explicit correction recipe of Appendix A.1 with the stability limit of
+ * Sec. 3.2.  nt_override > 0 fixes nt (rejected with WH_EUNSTABLE if the
+ * resulting dt breaks the limit), otherwise nt = max(5, ceil(T / dt_max)),
+ * raised until dt meets the limit; alpha < 0 selects alpha_d. */
+WH_API wh_status wh_compute_time_params(int32_t dim, const int64_t n[3], int32_t order, double c2max,
+                                 double omega, int32_t periods, double cfl_frac,
+                                 int32_t nt_override, double alpha, wh_time_params *out);
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL
+ * for the null stream), e.g. torch.cuda.current_stream().cuda_stream.
+ * *out is set on success and must be released with wh_destroy. */
+WH_API wh_status wh_create(wh_ctx **out, int32_t device, void *stream);
+
+/* Release a context (NULL is accepted).  Does not free the bound workspace. */
+WH_API void wh_destroy(wh_ctx *ctx);
+
+/* Message of the last failure on ctx ("" if none; static text if ctx is NULL). */
+WH_API const char *wh_last_error(const wh_ctx *ctx);
+
+/* Define the grid: dim in {2,3}, n[0..dim-1] cells per axis (each >= 2;
+ * n[2] ignored for dim = 2), order in {2,4}, precision a wh_precision.
+ * Resets c^2, the source, the frequency and the workspace binding. */
+WH_API wh_status wh_set_grid(wh_ctx *ctx, int32_t dim, const int64_t n[3], int32_t order, int32_t precision);
+
+/* Bytes of device workspace needed for the current grid when GMRES with
+ * restart length gmres_restart will be used (0 = no GMRES: applies and FPI). */
+WH_API wh_status wh_workspace_size(const wh_ctx *ctx, int32_t gmres_restart, size_t *bytes);
+
+/* Bind caller-owned device memory (256-byte aligned) as workspace.  The
+ * restart length later passed to wh_solve must not exceed the one the size
+ * was computed for. */
+WH_API wh_status wh_bind_workspace(wh_ctx *ctx, void *device_ptr, size_t bytes, int32_t gmres_restart);
+
+/* Wave speed squared at every node (host or device, flag on_device); must be
+ * finite and > 0 on interior nodes.  Copied into the workspace. */
+WH_API wh_status wh_set_c2(wh_ctx *ctx, const double *c2, int32_t on_device);
+
+/* Constant wave speed squared c2 > 0 (no per-node array is stored or read). */
+WH_API wh_status wh_set_c2_constant(wh_ctx *ctx, double c2);
+
+/* Helmholtz right-hand side f of the problem above (host or device). */
+WH_API wh_status wh_set_source(wh_ctx *ctx, const double *f, int32_t on_device);
+
+/* Frequency omega > 0, periods Np >= 1 per application, cfl_frac in (0, 1]
+ * of the stability limit, nt_override (0 = automatic), alpha (< 0 = alpha_d).
+ * Requires the grid and c^2. */
+WH_API wh_status wh_set_frequency(wh_ctx *ctx, double omega, int32_t periods, double cfl_frac,
+                           int32_t nt_override, double alpha);
+
+WH_API wh_status wh_get_time_params(const wh_ctx *ctx, wh_time_params *out);
+
+/* One WaveHoltz application (Alg. 1 loop body): W^0 = w0 (device), zero
+ * initial velocity, Np * nt leapfrog steps with forcing -s f cos(omega_e t^n)
+ * (s = with_forcing != 0), writing the filtered result
+ *   filtered = sum_n w_n W^n,  w_n = (2/(Np nt)) sigma_n (cos(omega_e t^n) - alpha/2),
+ * and the last state W^{Np nt} into w_final.  Both outputs are device
+ * pointers; either may be NULL.  Outputs may not alias w0. */
+WH_API wh_status wh_run_periods(wh_ctx *ctx, const double *w0, int32_t with_forcing, double *w_final,
+                         double *filtered);
+
+/* out = W_h(v, s f) (device pointers; out may not alias v). */
+WH_API wh_status wh_apply(wh_ctx *ctx, const double *v, double *out, int32_t with_forcing);
+
+/* Av = v - W_h(v, 0), the matrix-free operator A = I - S_h of Sec. 5.3
+ * (eq. MevalII).  Device pointers; Av may not alias v. */
+WH_API wh_status wh_apply_A(wh_ctx *ctx, const double *v, double *Av);
+
+/* Solve (I - S_h) v = b, b = W_h(0, f), by FPI (Alg. 1) or restarted GMRES.
+ * v (device) holds the initial guess on entry and the iterate on exit.
+ * info (nullable) receives the statistics.  Returns WH_ENOTCONV if rtol > 0
+ * was not reached within maxit (v still holds the last iterate),
+ * WH_ENONFINITE if a residual became NaN/Inf. */
+WH_API wh_status wh_solve(wh_ctx *ctx, const wh_solve_opts *opts, double *v, wh_solve_info *info);
+
+/* Diagnostic: res = c^2 Delta_{h,p} u + omega^2 u - f on interior nodes,
+ * 0 on the walls (device pointers; res may be NULL), and *rel =
+ * ||res||_2 / ||f||_2 (host, nullable).  Synchronises the stream. */
+WH_API wh_status wh_helmholtz_residual(wh_ctx *ctx, const double *u, double *res, double *rel);
+
+/* Diagnostic: *out = sum_i x_i y_i over all nodes (device inputs), with the
+ * library's deterministic reduction order.  Synchronises the stream. */
+WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *out);
+
+/* Tuning of the time-stepping kernels: kblock = leapfrog steps fused per
+ * pass over the grid (1..8; 0 = automatic), tile_x/tile_y = owned tile
+ * shape of a work-group in nodes (0 = automatic).  Results do not depend on
+ * these values beyond floating-point reassociation-free identity: every
+ * setting computes the same arithmetic per node and step. */
+WH_API wh_status wh_set_tuning(wh_ctx *ctx, int32_t kblock, int32_t tile_x, int32_t tile_y);
+
+/* Current tuning after automatic choices have been resolved for this grid. */
+WH_API wh_status wh_get_tuning(const wh_ctx *ctx, int32_t *kblock, int32_t *tile_x, int32_t *tile_y);
+
+/* Timing of the time-stepping kernels, measured with HIP events recorded on
+ * the context's stream around the leapfrog launches of every application
+ * (the first-step launch excluded).  Used for roofline reporting.
+ *   applies      applications timed
+ *   launches     leapfrog kernel launches timed
+ *   ms           their total device time in milliseconds
+ *   bytes        algorithmic HBM bytes those launches must move: every array
+ *                a launch reads or writes counted once per interior node
+ *                (state levels, c^2 if it varies, f if forced, the FP64
+ *                accumulator; the output and v on the last launch)
+ *   point_steps  interior-node time steps those launches performed */
+typedef struct {
+  int64_t applies;
+  int64_t launches;
+  double ms;
+  double bytes;
+  double point_steps;
+} wh_profile;
+
+/* enable != 0 resets the counters and starts recording; 0 stops.  Recording
+ * adds two event records per application and synchronises the stream every
+ * 256 applications. */
+WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
+
+/* Synchronise the stream and return the counters accumulated so far. */
+WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WH_H */

@@ -1,0 +1,928 @@
+// C ABI of the WaveHoltz library: context, validation, time parameters,
+// workspace layout, one WaveHoltz application, and the outer solvers
+// (fixed-point iteration of Alg. 1 and restarted GMRES on (I - S_h) v = b,
+// Sec. 5.3).  All grid-sized work runs in the HIP kernels; this file only
+// sequences launches and does O(restart^2) host arithmetic (Hessenberg,
+// Givens rotations).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wh.h"
+#include "wh_internal.h"
+
+struct wh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  bool grid_set = false;
+  int dim = 0, order = 0, prec = WH_FP64;
+  int64_t n[3] = {0, 0, 0};
+  int64_t nodes = 0;
+
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int ws_restart = 0;
+  void *c2 = nullptr;
+  void *f = nullptr;
+  void *W[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *acc = nullptr, *tmp = nullptr, *b = nullptr, *V = nullptr, *partials = nullptr, *scal = nullptr;
+  int64_t ldv = 0;
+
+  bool c2_set = false, c2_is_const = false;
+  double c2_value = 1.0, c2max = 1.0;
+  bool f_set = false;
+  bool freq_set = false;
+  wh_time_params tp{};
+  std::vector<double> wts;   // filter weight of level n, n = 0..N
+  std::vector<double> frc;   // -dt^2 cos(omega_e t^n), n = 0..N-1
+
+  int kblock = 0, tile_x = 0, tile_y = 0;
+  double *pinned = nullptr;  // host staging for reduction results
+  size_t pinned_count = 0;
+
+  struct Timed {
+    hipEvent_t a, b;
+    int64_t launches;
+    double bytes, point_steps;
+  };
+  bool profiling = false;
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> event_pool;
+  wh_profile prof{};
+};
+
+namespace {
+
+constexpr int kMaxScalars = 4 * (WH_MAX_RESTART + 2);
+
+wh_status fail(wh_ctx *ctx, wh_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+#define WH_HIP(ctx, call)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail((ctx), WH_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));               \
+  } while (0)
+
+#define WH_TRY(expr)                 \
+  do {                               \
+    wh_status s_ = (expr);           \
+    if (s_ != WH_OK) return s_;      \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t state_bytes(const wh_ctx *c) { return c->prec == WH_FP32_STATE ? 4 : 8; }
+
+struct Layout {
+  size_t c2, f, W[4], acc, tmp, b, V, partials, scal, total;
+  int64_t ldv;
+};
+
+Layout layout(const wh_ctx *c, int restart) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t nb = (size_t)c->nodes;
+  const size_t T = state_bytes(c);
+  L.c2 = take(nb * T);
+  L.f = take(nb * T);
+  for (int i = 0; i < 4; ++i) L.W[i] = take(nb * T);
+  L.acc = take(nb * 8);
+  L.tmp = take(nb * 8);
+  L.b = take(nb * 8);
+  L.ldv = (int64_t)(align256(nb * 8) / 8);
+  L.V = take(restart > 0 ? (size_t)(restart + 1) * (size_t)L.ldv * 8 : 0);
+  const int rows = std::max(restart + 1, 3);
+  L.partials = take((size_t)rows * (size_t)wh::reduction_blocks(c->nodes) * 8);
+  L.scal = take((size_t)kMaxScalars * 8);
+  L.total = off;
+  return L;
+}
+
+// Geometry with the stencil scaled by `scale` (dt^2 for the steps, dt^2/2
+// for the first step, 1 for the Helmholtz residual).
+wh::StepGeom geometry(const wh_ctx *c, double scale) {
+  wh::StepGeom g{};
+  g.dim = c->dim;
+  g.order = c->order;
+  g.nx = (int)c->n[0];
+  g.ny = (int)c->n[1];
+  g.nz = c->dim == 3 ? (int)c->n[2] : 0;
+  g.sy = c->n[0] + 1;
+  g.sz = (c->n[0] + 1) * (c->n[1] + 1);
+  g.nodes = c->nodes;
+  const double div = c->order == 4 ? 12.0 : 1.0;
+  const double centre = c->order == 4 ? 30.0 : 2.0;
+  g.kx = scale * (double)c->n[0] * (double)c->n[0] / div;
+  g.ky = scale * (double)c->n[1] * (double)c->n[1] / div;
+  g.kz = c->dim == 3 ? scale * (double)c->n[2] * (double)c->n[2] / div : 0.0;
+  g.kc = centre * (g.kx + g.ky + g.kz);
+  g.c2const = c->c2_value;
+  return g;
+}
+
+wh_status need(wh_ctx *c, bool grid, bool ws, bool c2, bool f, bool freq) {
+  if (!c) return WH_EINVAL;
+  if (grid && !c->grid_set) return fail(c, WH_ESTATE, "grid not set (call wh_set_grid first)");
+  if (ws && !c->ws) return fail(c, WH_ENOMEM, "no workspace bound (call wh_bind_workspace)");
+  if (c2 && !c->c2_set) return fail(c, WH_ESTATE, "c^2 not set (call wh_set_c2 or wh_set_c2_constant)");
+  if (f && !c->f_set) return fail(c, WH_ESTATE, "source not set (call wh_set_source)");
+  if (freq && !c->freq_set) return fail(c, WH_ESTATE, "frequency not set (call wh_set_frequency)");
+  return WH_OK;
+}
+
+wh_status set_device(wh_ctx *c) {
+  WH_HIP(c, hipSetDevice(c->device));
+  return WH_OK;
+}
+
+// Reduce `k` rows of partials into scal[dst..dst+k) on the device.
+wh_status reduce_to(wh_ctx *c, int k, int dst) {
+  const int nb = wh::reduction_blocks(c->nodes);
+  WH_HIP(c, wh::launch_reduce_rows(c->partials, nb, k, c->scal + dst, c->stream));
+  return WH_OK;
+}
+
+wh_status fetch_scalars(wh_ctx *c, int first, int count, double *out) {
+  WH_HIP(c, hipMemcpyAsync(c->pinned, c->scal + first, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream));
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  std::memcpy(out, c->pinned, (size_t)count * 8);
+  return WH_OK;
+}
+
+// sum_e x_e y_e -> scal[dst] (device), deterministic.
+wh_status dot_dev(wh_ctx *c, const double *x, const double *y, int dst) {
+  const int nb = wh::reduction_blocks(c->nodes);
+  WH_HIP(c, wh::launch_mdot(x, 0, 1, y, c->nodes, c->partials, nb, c->stream));
+  return reduce_to(c, 1, dst);
+}
+
+// Is ptr device memory usable on ctx->device?
+bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+wh_status check_dev(wh_ctx *c, const void *p, const char *name) {
+  if (!p) return fail(c, WH_EINVAL, "%s is NULL", name);
+  if (!is_device_ptr(p)) return fail(c, WH_EINVAL, "%s is not device memory", name);
+  return WH_OK;
+}
+
+// Copy a caller node array (host or device, FP64) into a workspace array in
+// state precision.
+wh_status upload_field(wh_ctx *c, const double *src, int on_device, void *dst) {
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  const size_t bytes = (size_t)c->nodes * 8;
+  if (on_device) {
+    if (fp32) {
+      WH_HIP(c, wh::launch_to_state(true, src, dst, c->nodes, c->stream));
+    } else {
+      WH_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+  } else {
+    if (fp32) {
+      // stage in the FP64 accumulator, then convert
+      WH_HIP(c, hipMemcpyAsync(c->acc, src, bytes, hipMemcpyHostToDevice, c->stream));
+      WH_HIP(c, wh::launch_to_state(true, c->acc, dst, c->nodes, c->stream));
+    } else {
+      WH_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    }
+    WH_HIP(c, hipStreamSynchronize(c->stream));  // the host buffer may be freed on return
+  }
+  return WH_OK;
+}
+
+void build_tables(wh_ctx *c) {
+  const int64_t nt = c->tp.nt, N = (int64_t)c->tp.nt * c->tp.periods;
+  const double two_pi = 2.0 * M_PI;
+  c->wts.assign((size_t)N + 1, 0.0);
+  c->frc.assign((size_t)N, 0.0);
+  const double norm = 2.0 / (double)N;
+  for (int64_t m = 0; m <= N; ++m) {
+    const double phase = std::cos(two_pi * (double)(m % nt) / (double)nt);
+    const double sigma = (m == 0 || m == N) ? 0.5 : 1.0;
+    c->wts[(size_t)m] = norm * sigma * (phase - 0.5 * c->tp.alpha);
+    if (m < N) c->frc[(size_t)m] = -c->tp.dt * c->tp.dt * phase;
+  }
+}
+
+double interior_nodes(const wh_ctx *c) {
+  double u = 1.0;
+  for (int m = 0; m < c->dim; ++m) u *= (double)(c->n[m] - 1);
+  return u;
+}
+
+wh_status take_events(wh_ctx *c, hipEvent_t *a, hipEvent_t *b) {
+  for (hipEvent_t *e : {a, b}) {
+    if (!c->event_pool.empty()) {
+      *e = c->event_pool.back();
+      c->event_pool.pop_back();
+    } else {
+      WH_HIP(c, hipEventCreate(e));
+    }
+  }
+  return WH_OK;
+}
+
+// Wait for the recorded applications and fold their times into the counters.
+wh_status drain_profile(wh_ctx *c) {
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto &t : c->pending) {
+    float ms = 0.0f;
+    WH_HIP(c, hipEventElapsedTime(&ms, t.a, t.b));
+    c->prof.applies += 1;
+    c->prof.launches += t.launches;
+    c->prof.ms += ms;
+    c->prof.bytes += t.bytes;
+    c->prof.point_steps += t.point_steps;
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->pending.clear();
+  return WH_OK;
+}
+
+// One WaveHoltz application.  mode: ACCUMULATE (acc keeps the filter),
+// FINAL_FILTER (out = filtered) or FINAL_A (out = v - filtered).
+wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double *out, double *w_final) {
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  const int64_t N = (int64_t)c->tp.nt * c->tp.periods;
+  const double dt2 = c->tp.dt * c->tp.dt;
+  const wh::StepGeom g = geometry(c, dt2);
+  const wh::StepGeom half = geometry(c, 0.5 * dt2);
+  const void *c2 = c->c2_is_const ? nullptr : c->c2;
+  const void *f = forcing ? c->f : nullptr;
+  WH_HIP(c, wh::launch_first_step(fp32, half, v, c->W[0], c->W[1], c->acc, c2, f, forcing ? -0.5 * dt2 : 0.0,
+                                  c->wts[0], c->wts[1], c->stream));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->profiling) {
+    WH_TRY(take_events(c, &ev0, &ev1));
+    WH_HIP(c, hipEventRecord(ev0, c->stream));
+  }
+  void *prev = c->W[0], *cur = c->W[1];
+  for (int64_t n = 1; n < N; ++n) {
+    const int m = (n == N - 1) ? mode : wh::ACCUMULATE;
+    WH_HIP(c, wh::launch_step(fp32, g, cur, prev, c->acc, c2, f, forcing ? c->frc[(size_t)n] : 0.0,
+                              c->wts[(size_t)n + 1], m, v, out, c->stream));
+    std::swap(prev, cur);
+  }
+  if (c->profiling) {
+    WH_HIP(c, hipEventRecord(ev1, c->stream));
+    const double interior = interior_nodes(c);
+    const double T = (double)state_bytes(c);
+    // per launch and interior node: W^n, W^{n-1} read, W^{n+1} written, c^2 and
+    // f read when present, FP64 accumulator read and written
+    const double per = 3.0 * T + (c2 ? T : 0.0) + (f ? T : 0.0) + 16.0;
+    const double extra = (mode == wh::FINAL_A) ? 8.0 : 0.0;  // v read on the last launch
+    c->pending.push_back({ev0, ev1, N - 1, interior * (per * (double)(N - 1) + extra),
+                          interior * (double)(N - 1)});
+    if (c->pending.size() >= 256) WH_TRY(drain_profile(c));
+  }
+  if (w_final) WH_HIP(c, wh::launch_from_state(fp32, cur, w_final, c->nodes, c->stream));
+  return WH_OK;
+}
+
+double point_steps_per_apply(const wh_ctx *c) {
+  double u = 1.0;
+  for (int m = 0; m < c->dim; ++m) u *= (double)(c->n[m] - 1);
+  return u * (double)c->tp.nt * (double)c->tp.periods;
+}
+
+// Library's own evaluation of the discrete filter function (three-sinc
+// form, Appendix A.3) for the predicted rate of Theorem 2.
+double sincd(double z, double T, double dt) {
+  const double t = std::tan(0.5 * z * dt);
+  if (std::fabs(t) < 1e-300) return 1.0;
+  return std::sin(z * T) / (T * t / (0.5 * dt));
+}
+
+double predicted_rate(const wh_ctx *c) {
+  if (!c->c2_is_const) return NAN;
+  double modes = 1.0;
+  for (int m = 0; m < c->dim; ++m) modes *= (double)(c->n[m] - 1);
+  if (modes > (double)(1 << 22)) return NAN;
+  const double dt = c->tp.dt, we = c->tp.omega_e, al = c->tp.alpha;
+  const double Tbar = (double)c->tp.nt * c->tp.periods * dt;
+  std::vector<double> ax[3];
+  for (int m = 0; m < c->dim; ++m) {
+    const double nn = (double)c->n[m];
+    for (int64_t k = 1; k < c->n[m]; ++k) {
+      const double s = std::sin(0.5 * M_PI * (double)k / nn);
+      const double s2 = s * s;
+      // eigenvalue of -d^2/dx^2 on sin(k pi x): 4 n^2 s^2 (p = 2), plus (4/3) n^2 s^4 (p = 4)
+      double lam = 4.0 * nn * nn * s2;
+      if (c->order == 4) lam += (4.0 / 3.0) * nn * nn * s2 * s2;
+      ax[m].push_back(lam);
+    }
+  }
+  double mu = 0.0;
+  const size_t nz = c->dim == 3 ? ax[2].size() : 1;
+  for (size_t kz = 0; kz < nz; ++kz)
+    for (double ly : ax[1])
+      for (double lx : ax[0]) {
+        const double lam2 = c->c2_value * (lx + ly + (c->dim == 3 ? ax[2][kz] : 0.0));
+        const double arg = 0.5 * std::sqrt(lam2) * dt;
+        if (arg >= 1.0) continue;
+        const double lt = (2.0 / dt) * std::asin(arg);
+        const double b = sincd(we + lt, Tbar, dt) + sincd(we - lt, Tbar, dt) - al * sincd(lt, Tbar, dt);
+        mu = std::max(mu, std::fabs(b));
+      }
+  return mu;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wh_version(void) { return 10000; }
+
+const char *wh_status_string(int32_t s) {
+  switch (s) {
+    case WH_OK: return "WH_OK";
+    case WH_EINVAL: return "WH_EINVAL";
+    case WH_ENOMEM: return "WH_ENOMEM";
+    case WH_EDEVICE: return "WH_EDEVICE";
+    case WH_EUNSTABLE: return "WH_EUNSTABLE";
+    case WH_ENOTCONV: return "WH_ENOTCONV";
+    case WH_ENONFINITE: return "WH_ENONFINITE";
+    case WH_ESTATE: return "WH_ESTATE";
+    default: return "unknown wh_status";
+  }
+}
+
+wh_status wh_compute_time_params(int32_t dim, const int64_t n[3], int32_t order, double c2max, double omega,
+                                 int32_t periods, double cfl_frac, int32_t nt_override, double alpha,
+                                 wh_time_params *out) {
+  if (!n || !out) return WH_EINVAL;
+  if (dim != 2 && dim != 3) return WH_EINVAL;
+  if (order != 2 && order != 4) return WH_EINVAL;
+  for (int m = 0; m < dim; ++m)
+    if (n[m] < 2 || n[m] > (int64_t)1 << 20) return WH_EINVAL;
+  if (!(c2max > 0.0) || !std::isfinite(c2max)) return WH_EINVAL;
+  if (!(omega > 0.0) || !std::isfinite(omega)) return WH_EINVAL;
+  if (periods < 1 || periods > 1000) return WH_EINVAL;
+  if (!(cfl_frac > 0.0) || cfl_frac > 1.0) return WH_EINVAL;
+  if (nt_override < 0 || (nt_override > 0 && nt_override < 5)) return WH_EINVAL;
+  if (!std::isfinite(alpha)) return WH_EINVAL;
+  const double limit = order == 2 ? 1.0 : std::sqrt(3.0) / 2.0;  // C_{2,p}
+  double root = 0.0;
+  for (int m = 0; m < dim; ++m) root += (double)n[m] * (double)n[m];
+  root = std::sqrt(root);
+  const double cmax = std::sqrt(c2max);
+  const double dt_max = cfl_frac * limit / (cmax * root);
+  int64_t nt;
+  if (nt_override > 0) {
+    nt = nt_override;
+    const double dt = (2.0 / omega) * std::sin(M_PI / (double)nt);
+    if (cmax * dt * root > limit * (1.0 + 1e-12)) return WH_EUNSTABLE;
+  } else {
+    const double est = std::ceil((2.0 * M_PI / omega) / dt_max);
+    if (!(est < 1e8)) return WH_EINVAL;
+    nt = std::max<int64_t>(5, (int64_t)est);
+    while ((2.0 / omega) * std::sin(M_PI / (double)nt) > dt_max) ++nt;
+  }
+  if (nt * (int64_t)periods > (int64_t)1 << 26) return WH_EINVAL;
+  const double dt = (2.0 / omega) * std::sin(M_PI / (double)nt);
+  out->nt = (int32_t)nt;
+  out->periods = periods;
+  out->dt = dt;
+  out->omega = omega;
+  out->omega_e = 2.0 * M_PI / ((double)nt * dt);
+  out->alpha = alpha < 0.0 ? std::tan(M_PI / (double)nt) / std::tan(2.0 * M_PI / (double)nt) : alpha;
+  out->cfl = cmax * dt * root;
+  out->c2max = c2max;
+  return WH_OK;
+}
+
+wh_status wh_create(wh_ctx **out, int32_t device, void *stream) {
+  if (!out) return WH_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return WH_EDEVICE;
+  }
+  wh_ctx *c = new (std::nothrow) wh_ctx();
+  if (!c) return WH_ENOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void **)&c->pinned, (size_t)kMaxScalars * 8, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return WH_EDEVICE;
+  }
+  c->pinned_count = kMaxScalars;
+  *out = c;
+  return WH_OK;
+}
+
+void wh_destroy(wh_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
+  for (auto &t : c->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+wh_status wh_profile_enable(wh_ctx *c, int32_t enable) {
+  if (!c) return WH_EINVAL;
+  WH_TRY(set_device(c));
+  if (!c->pending.empty()) WH_TRY(drain_profile(c));
+  if (enable) c->prof = wh_profile{};
+  c->profiling = enable != 0;
+  return WH_OK;
+}
+
+wh_status wh_profile_read(wh_ctx *c, wh_profile *out) {
+  if (!c || !out) return WH_EINVAL;
+  WH_TRY(set_device(c));
+  if (!c->pending.empty()) WH_TRY(drain_profile(c));
+  *out = c->prof;
+  return WH_OK;
+}
+
+const char *wh_last_error(const wh_ctx *c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+wh_status wh_set_grid(wh_ctx *c, int32_t dim, const int64_t n[3], int32_t order, int32_t precision) {
+  if (!c) return WH_EINVAL;
+  if (dim != 2 && dim != 3) return fail(c, WH_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+  if (!n) return fail(c, WH_EINVAL, "n is NULL");
+  if (order != 2 && order != 4) return fail(c, WH_EINVAL, "order must be 2 or 4 (got %d)", order);
+  if (precision != WH_FP64 && precision != WH_FP32_STATE)
+    return fail(c, WH_EINVAL, "precision must be WH_FP64 or WH_FP32_STATE");
+  int64_t nodes = 1;
+  for (int m = 0; m < dim; ++m) {
+    if (n[m] < 2 || n[m] > 65535) return fail(c, WH_EINVAL, "n[%d] = %lld out of range [2, 65535]", m, (long long)n[m]);
+    nodes *= n[m] + 1;
+  }
+  if (nodes > ((int64_t)1 << 33)) return fail(c, WH_EINVAL, "grid too large (%lld nodes)", (long long)nodes);
+  c->grid_set = true;
+  c->dim = dim;
+  c->order = order;
+  c->prec = precision;
+  c->n[0] = n[0];
+  c->n[1] = n[1];
+  c->n[2] = dim == 3 ? n[2] : 0;
+  c->nodes = nodes;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->c2_set = c->f_set = c->freq_set = false;
+  c->c2_is_const = false;
+  c->kblock = c->tile_x = c->tile_y = 0;
+  c->err.clear();
+  return WH_OK;
+}
+
+wh_status wh_workspace_size(const wh_ctx *c, int32_t restart, size_t *bytes) {
+  if (!c || !bytes) return WH_EINVAL;
+  if (!c->grid_set) return WH_ESTATE;
+  if (restart < 0 || restart > WH_MAX_RESTART) return WH_EINVAL;
+  *bytes = layout(c, restart).total;
+  return WH_OK;
+}
+
+wh_status wh_bind_workspace(wh_ctx *c, void *ptr, size_t bytes, int32_t restart) {
+  WH_TRY(need(c, true, false, false, false, false));
+  if (restart < 0 || restart > WH_MAX_RESTART) return fail(c, WH_EINVAL, "restart out of range");
+  if (!ptr) return fail(c, WH_EINVAL, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return fail(c, WH_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = layout(c, restart);
+  if (bytes < L.total)
+    return fail(c, WH_ENOMEM, "workspace too small: %zu bytes given, %zu needed", bytes, L.total);
+  WH_TRY(set_device(c));
+  if (!is_device_ptr(ptr)) return fail(c, WH_EINVAL, "workspace is not device memory");
+  char *base = static_cast<char *>(ptr);
+  c->ws = base;
+  c->ws_bytes = bytes;
+  c->ws_restart = restart;
+  c->c2 = base + L.c2;
+  c->f = base + L.f;
+  for (int i = 0; i < 4; ++i) c->W[i] = base + L.W[i];
+  c->acc = reinterpret_cast<double *>(base + L.acc);
+  c->tmp = reinterpret_cast<double *>(base + L.tmp);
+  c->b = reinterpret_cast<double *>(base + L.b);
+  c->V = restart > 0 ? reinterpret_cast<double *>(base + L.V) : nullptr;
+  c->ldv = L.ldv;
+  c->partials = reinterpret_cast<double *>(base + L.partials);
+  c->scal = reinterpret_cast<double *>(base + L.scal);
+  c->c2_set = c->f_set = c->freq_set = false;
+  return WH_OK;
+}
+
+static wh_status finish_c2(wh_ctx *c) {
+  // Any change of c^2 invalidates the time parameters.
+  c->freq_set = false;
+  c->c2_set = true;
+  return WH_OK;
+}
+
+wh_status wh_set_c2_constant(wh_ctx *c, double c2) {
+  WH_TRY(need(c, true, true, false, false, false));
+  if (!(c2 > 0.0) || !std::isfinite(c2)) return fail(c, WH_EINVAL, "c2 must be finite and > 0");
+  c->c2_is_const = true;
+  c->c2_value = c2;
+  c->c2max = c2;
+  return finish_c2(c);
+}
+
+wh_status wh_set_c2(wh_ctx *c, const double *c2, int32_t on_device) {
+  WH_TRY(need(c, true, true, false, false, false));
+  if (!c2) return wh_set_c2_constant(c, 1.0);
+  WH_TRY(set_device(c));
+  if (on_device) WH_TRY(check_dev(c, c2, "c2"));
+  // stats on the FP64 values: stage through the accumulator when on host
+  const double *src = c2;
+  if (!on_device) {
+    WH_HIP(c, hipMemcpyAsync(c->acc, c2, (size_t)c->nodes * 8, hipMemcpyHostToDevice, c->stream));
+    src = c->acc;
+  }
+  const int nb = wh::reduction_blocks(c->nodes);
+  const wh::StepGeom g = geometry(c, 1.0);
+  WH_HIP(c, wh::launch_interior_stats(g, src, c->partials, nb, c->stream));
+  std::vector<double> part((size_t)3 * nb);
+  WH_HIP(c, hipMemcpyAsync(part.data(), c->partials, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  double mx = -INFINITY, mn = INFINITY, bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    mx = std::max(mx, part[3 * b]);
+    mn = std::min(mn, part[3 * b + 1]);
+    bad += part[3 * b + 2];
+  }
+  if (bad > 0.0) return fail(c, WH_EINVAL, "c2 has %.0f non-finite interior values", bad);
+  if (!(mn > 0.0)) return fail(c, WH_EINVAL, "c2 must be > 0 on interior nodes (min %g)", mn);
+  if (c->prec == WH_FP32_STATE) {
+    WH_HIP(c, wh::launch_to_state(true, src, c->c2, c->nodes, c->stream));
+  } else {
+    WH_HIP(c, hipMemcpyAsync(c->c2, src, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  c->c2_is_const = false;
+  c->c2_value = 1.0;
+  c->c2max = mx;
+  return finish_c2(c);
+}
+
+wh_status wh_set_source(wh_ctx *c, const double *f, int32_t on_device) {
+  WH_TRY(need(c, true, true, false, false, false));
+  if (!f) return fail(c, WH_EINVAL, "f is NULL");
+  WH_TRY(set_device(c));
+  if (on_device) WH_TRY(check_dev(c, f, "f"));
+  WH_TRY(upload_field(c, f, on_device, c->f));
+  c->f_set = true;
+  return WH_OK;
+}
+
+wh_status wh_set_frequency(wh_ctx *c, double omega, int32_t periods, double cfl_frac, int32_t nt_override,
+                           double alpha) {
+  WH_TRY(need(c, true, true, true, false, false));
+  wh_time_params tp{};
+  const wh_status st =
+      wh_compute_time_params(c->dim, c->n, c->order, c->c2max, omega, periods, cfl_frac, nt_override, alpha, &tp);
+  if (st == WH_EUNSTABLE)
+    return fail(c, st, "nt = %d violates the explicit stability limit for this grid and c^2", nt_override);
+  if (st != WH_OK) return fail(c, st, "invalid frequency parameters (omega %g, periods %d, cfl %g, nt %d)", omega,
+                                periods, cfl_frac, nt_override);
+  c->tp = tp;
+  build_tables(c);
+  c->freq_set = true;
+  return WH_OK;
+}
+
+wh_status wh_get_time_params(const wh_ctx *c, wh_time_params *out) {
+  if (!c || !out) return WH_EINVAL;
+  if (!c->freq_set) return WH_ESTATE;
+  *out = c->tp;
+  return WH_OK;
+}
+
+wh_status wh_run_periods(wh_ctx *c, const double *w0, int32_t with_forcing, double *w_final, double *filtered) {
+  WH_TRY(need(c, true, true, true, with_forcing != 0, true));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, w0, "w0"));
+  if (w_final) WH_TRY(check_dev(c, w_final, "w_final"));
+  if (filtered) WH_TRY(check_dev(c, filtered, "filtered"));
+  if (w_final == w0 || filtered == w0) return fail(c, WH_EINVAL, "outputs may not alias w0");
+  return apply_impl(c, w0, with_forcing != 0, filtered ? wh::FINAL_FILTER : wh::ACCUMULATE, filtered, w_final);
+}
+
+wh_status wh_apply(wh_ctx *c, const double *v, double *out, int32_t with_forcing) {
+  WH_TRY(need(c, true, true, true, with_forcing != 0, true));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, v, "v"));
+  WH_TRY(check_dev(c, out, "out"));
+  if (out == v) return fail(c, WH_EINVAL, "out may not alias v");
+  return apply_impl(c, v, with_forcing != 0, wh::FINAL_FILTER, out, nullptr);
+}
+
+wh_status wh_apply_A(wh_ctx *c, const double *v, double *Av) {
+  WH_TRY(need(c, true, true, true, false, true));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, v, "v"));
+  WH_TRY(check_dev(c, Av, "Av"));
+  if (Av == v) return fail(c, WH_EINVAL, "Av may not alias v");
+  return apply_impl(c, v, false, wh::FINAL_A, Av, nullptr);
+}
+
+wh_status wh_dot(wh_ctx *c, const double *x, const double *y, double *out) {
+  WH_TRY(need(c, true, true, false, false, false));
+  if (!out) return fail(c, WH_EINVAL, "out is NULL");
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, x, "x"));
+  WH_TRY(check_dev(c, y, "y"));
+  WH_TRY(dot_dev(c, x, y, 0));
+  return fetch_scalars(c, 0, 1, out);
+}
+
+wh_status wh_helmholtz_residual(wh_ctx *c, const double *u, double *res, double *rel) {
+  WH_TRY(need(c, true, true, true, true, true));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, u, "u"));
+  if (res) WH_TRY(check_dev(c, res, "res"));
+  double *r = res ? res : c->tmp;
+  if (r == u) return fail(c, WH_EINVAL, "res may not alias u");
+  const wh::StepGeom g = geometry(c, 1.0);
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  const double om = c->tp.omega;
+  WH_HIP(c, wh::launch_helmholtz_residual(g, u, c->c2_is_const ? nullptr : c->c2, fp32, c->f, fp32, om * om, r,
+                                          c->stream));
+  if (rel) {
+    // ||f||: f lives in state precision; convert into acc for the dot
+    WH_HIP(c, wh::launch_from_state(fp32, c->f, c->acc, c->nodes, c->stream));
+    WH_TRY(dot_dev(c, r, r, 0));
+    WH_TRY(dot_dev(c, c->acc, c->acc, 1));
+    double s[2];
+    WH_TRY(fetch_scalars(c, 0, 2, s));
+    *rel = s[1] > 0.0 ? std::sqrt(s[0] / s[1]) : std::sqrt(s[0]);
+  }
+  return WH_OK;
+}
+
+wh_status wh_set_tuning(wh_ctx *c, int32_t kblock, int32_t tile_x, int32_t tile_y) {
+  WH_TRY(need(c, true, false, false, false, false));
+  if (kblock < 0 || kblock > 8) return fail(c, WH_EINVAL, "kblock must be in 0..8");
+  if (tile_x < 0 || tile_y < 0 || tile_x > 1024 || tile_y > 1024) return fail(c, WH_EINVAL, "bad tile shape");
+  c->kblock = kblock;
+  c->tile_x = tile_x;
+  c->tile_y = tile_y;
+  return WH_OK;
+}
+
+wh_status wh_get_tuning(const wh_ctx *c, int32_t *kblock, int32_t *tile_x, int32_t *tile_y) {
+  if (!c || !kblock || !tile_x || !tile_y) return WH_EINVAL;
+  if (!c->grid_set) return WH_ESTATE;
+  *kblock = c->kblock > 0 ? c->kblock : 1;
+  *tile_x = c->tile_x;
+  *tile_y = c->tile_y;
+  return WH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solvers
+// ---------------------------------------------------------------------------
+static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
+  const int nb = wh::reduction_blocks(c->nodes);
+  // ||b||: b = W_h(0, f); when the initial guess is zero the first iterate is b
+  double vv;
+  WH_TRY(dot_dev(c, v, v, 0));
+  WH_TRY(fetch_scalars(c, 0, 1, &vv));
+  if (!std::isfinite(vv)) return fail(c, WH_ENONFINITE, "initial guess is not finite");
+  double bnorm = -1.0;
+  int applies = 0;
+  if (vv != 0.0) {
+    WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
+    WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));
+    ++applies;
+    double bb;
+    WH_TRY(dot_dev(c, c->b, c->b, 0));
+    WH_TRY(fetch_scalars(c, 0, 1, &bb));
+    bnorm = std::sqrt(bb);
+  }
+  double r_first = 0.0, r_prev = 0.0, r_last = 0.0;
+  int k = 0;
+  wh_status st = WH_OK;
+  for (k = 1; k <= o->maxit; ++k) {
+    WH_TRY(apply_impl(c, v, true, wh::FINAL_FILTER, c->tmp, nullptr));
+    ++applies;
+    WH_HIP(c, wh::launch_diff_norm_copy(c->tmp, v, c->nodes, c->partials, nb, c->stream));
+    WH_TRY(reduce_to(c, 1, 0));
+    double rr;
+    WH_TRY(fetch_scalars(c, 0, 1, &rr));
+    const double r = std::sqrt(rr);
+    if (!std::isfinite(r)) {
+      st = fail(c, WH_ENONFINITE, "FPI residual became non-finite at iteration %d", k);
+      break;
+    }
+    if (bnorm < 0.0) bnorm = r;  // zero initial guess: v^1 - v^0 = b
+    if (k == 1) r_first = r;
+    r_prev = r_last;
+    r_last = r;
+    const double rel = bnorm > 0.0 ? r / bnorm : 0.0;
+    if (o->on_iter) o->on_iter(k, rel, o->user);
+    if (o->rtol > 0.0 && rel <= o->rtol) break;
+  }
+  if (k > o->maxit) k = o->maxit;
+  if (info) {
+    info->iters = k;
+    info->applies = applies;
+    info->bnorm = bnorm;
+    info->rel_res = bnorm > 0.0 ? r_last / bnorm : 0.0;
+    info->scaled_res = r_last / std::sqrt((double)c->nodes);
+    info->cr_last = (k >= 2 && r_prev > 0.0) ? r_last / r_prev : NAN;
+    info->cr_avg = (k >= 2 && r_first > 0.0) ? std::pow(r_last / r_first, 1.0 / (k - 1)) : NAN;
+    info->ecr = std::pow(info->cr_avg, 1.0 / c->tp.periods);
+    info->point_steps = applies * point_steps_per_apply(c);
+  }
+  if (st == WH_OK && o->rtol > 0.0 && !(bnorm > 0.0 ? r_last / bnorm <= o->rtol : true))
+    st = fail(c, WH_ENOTCONV, "FPI reached maxit = %d at relative residual %g", o->maxit,
+              bnorm > 0.0 ? r_last / bnorm : 0.0);
+  return st;
+}
+
+static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info) {
+  const int m = o->restart;
+  if (m < 1 || m > c->ws_restart)
+    return fail(c, WH_EINVAL, "restart %d must be in 1..%d (the workspace's restart length)", m, c->ws_restart);
+  const int64_t N = c->nodes;
+  const int nb = wh::reduction_blocks(N);
+  auto Vj = [&](int j) { return c->V + (int64_t)j * c->ldv; };
+  // scalar slots on the device
+  const int S_H1 = 0, S_H2 = m + 2, S_NRM = 2 * (m + 2);
+
+  int applies = 0;
+  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, N, c->stream));
+  WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));  // b = W_h(0, f)
+  ++applies;
+  double bb;
+  WH_TRY(dot_dev(c, c->b, c->b, S_NRM));
+  WH_TRY(fetch_scalars(c, S_NRM, 1, &bb));
+  const double bnorm = std::sqrt(bb);
+  if (!std::isfinite(bnorm)) return fail(c, WH_ENONFINITE, "||b|| is not finite");
+
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(2 * (m + 2) + 1);
+  auto Hat = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+
+  int total = 0;
+  double rel = 0.0, r0_first = -1.0;
+  wh_status st = WH_OK;
+  bool done = false;
+  // r = b - A x into V_0
+  WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
+  ++applies;
+  WH_HIP(c, wh::launch_sub(c->b, c->tmp, Vj(0), N, c->stream));
+  while (!done) {
+    double rr;
+    WH_TRY(dot_dev(c, Vj(0), Vj(0), S_NRM));
+    WH_TRY(fetch_scalars(c, S_NRM, 1, &rr));
+    const double beta = std::sqrt(rr);
+    if (!std::isfinite(beta)) {
+      st = fail(c, WH_ENONFINITE, "GMRES residual became non-finite");
+      break;
+    }
+    rel = bnorm > 0.0 ? beta / bnorm : 0.0;
+    if (r0_first < 0.0) r0_first = rel;
+    if (bnorm == 0.0 || rel <= o->rtol || total >= o->maxit) break;
+    WH_HIP(c, wh::launch_scale_by_rnorm(Vj(0), Vj(0), c->scal + S_NRM, N, c->stream));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kused = 0;
+    for (int j = 0; j < m && total < o->maxit; ++j) {
+      double *w = Vj(j + 1);
+      WH_TRY(apply_impl(c, Vj(j), false, wh::FINAL_A, w, nullptr));
+      ++applies;
+      // classical Gram-Schmidt, twice (coefficients stay on the device between passes)
+      WH_HIP(c, wh::launch_mdot(c->V, c->ldv, j + 1, w, N, c->partials, nb, c->stream));
+      WH_TRY(reduce_to(c, j + 1, S_H1));
+      WH_HIP(c, wh::launch_block_axpy(c->V, c->ldv, j + 1, c->scal + S_H1, w, N, c->stream));
+      WH_HIP(c, wh::launch_mdot(c->V, c->ldv, j + 1, w, N, c->partials, nb, c->stream));
+      WH_TRY(reduce_to(c, j + 1, S_H2));
+      WH_HIP(c, wh::launch_block_axpy(c->V, c->ldv, j + 1, c->scal + S_H2, w, N, c->stream));
+      WH_TRY(dot_dev(c, w, w, S_NRM));
+      WH_TRY(fetch_scalars(c, 0, S_NRM + 1, h.data()));
+      const double hn = std::sqrt(h[S_NRM]);
+      for (int i = 0; i <= j; ++i) Hat(i, j) = h[S_H1 + i] + h[S_H2 + i];
+      Hat(j + 1, j) = hn;
+      if (!std::isfinite(hn)) {
+        st = fail(c, WH_ENONFINITE, "GMRES Arnoldi vector became non-finite");
+        done = true;
+        break;
+      }
+      if (hn > 0.0) WH_HIP(c, wh::launch_scale_by_rnorm(w, w, c->scal + S_NRM, N, c->stream));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+        Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+        Hat(i, j) = t;
+      }
+      const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
+      cs[j] = den > 0.0 ? Hat(j, j) / den : 1.0;
+      sn[j] = den > 0.0 ? Hat(j + 1, j) / den : 0.0;
+      Hat(j, j) = den;
+      Hat(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      kused = j + 1;
+      const double est = bnorm > 0.0 ? std::fabs(g[j + 1]) / bnorm : 0.0;
+      if (o->on_iter) o->on_iter(total, est, o->user);
+      if (est <= o->rtol || hn == 0.0) break;
+    }
+    if (st != WH_OK) break;
+    if (kused == 0) break;
+    // y = R^{-1} g, x += V y
+    for (int i = kused - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < kused; ++l) s -= Hat(i, l) * y[l];
+      y[i] = s / Hat(i, i);
+    }
+    std::memcpy(c->pinned, y.data(), (size_t)kused * 8);
+    WH_HIP(c, hipMemcpyAsync(c->scal + S_H1, c->pinned, (size_t)kused * 8, hipMemcpyHostToDevice, c->stream));
+    WH_HIP(c, wh::launch_block_gemv_add(c->V, c->ldv, kused, c->scal + S_H1, x, N, c->stream));
+    // true residual, also the next cycle's starting vector
+    WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
+    ++applies;
+    WH_HIP(c, wh::launch_sub(c->b, c->tmp, Vj(0), N, c->stream));
+  }
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->iters = total;
+    info->applies = applies;
+    info->bnorm = bnorm;
+    info->rel_res = rel;
+    info->scaled_res = rel * bnorm / std::sqrt((double)N);
+    info->cr_last = (total > 0 && r0_first > 0.0) ? std::pow(rel / r0_first, 1.0 / total) : NAN;
+    info->cr_avg = info->cr_last;
+    info->ecr = std::pow(info->cr_avg, 1.0 / c->tp.periods);
+    info->point_steps = applies * point_steps_per_apply(c);
+  }
+  if (st == WH_OK && rel > o->rtol)
+    st = fail(c, WH_ENOTCONV, "GMRES reached maxit = %d at relative residual %g", o->maxit, rel);
+  return st;
+}
+
+wh_status wh_solve(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
+  WH_TRY(need(c, true, true, true, true, true));
+  if (!o) return fail(c, WH_EINVAL, "opts is NULL");
+  if (o->flags != 0) return fail(c, WH_EINVAL, "opts.flags must be 0");
+  if (o->maxit < 1) return fail(c, WH_EINVAL, "maxit must be >= 1");
+  if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(c, WH_EINVAL, "rtol must be finite and >= 0");
+  if (o->method != WH_SOLVER_FPI && o->method != WH_SOLVER_GMRES) return fail(c, WH_EINVAL, "unknown method");
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, v, "v"));
+  if (info) std::memset(info, 0, sizeof *info);
+  const auto t0 = std::chrono::steady_clock::now();
+  wh_status st;
+  try {
+    st = o->method == WH_SOLVER_FPI ? solve_fpi(c, o, v, info) : solve_gmres(c, o, v, info);
+  } catch (const std::bad_alloc &) {
+    st = fail(c, WH_ENOMEM, "host allocation failed");
+  } catch (...) {
+    st = fail(c, WH_EDEVICE, "unexpected exception");
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && st == WH_OK)
+    st = fail(c, WH_EDEVICE, "stream synchronisation failed");
+  if (info) {
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->mu_pred = predicted_rate(c);
+  }
+  return st;
+}
+
+}  // extern "C"

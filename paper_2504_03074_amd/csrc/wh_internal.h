@@ -1,0 +1,89 @@
+// Internal interface between the C-ABI layer (wh_api.cpp) and the HIP kernels
+// (wh_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <cstdint>
+
+namespace wh {
+
+// Geometry and per-step coefficients of one leapfrog launch.
+//   next = 2 cur - prev + c2 * (sum_m k_m * S_m(cur) - kc * cur) + gn * f
+// where S_m is the symmetric neighbour sum along axis m:
+//   p = 2: W[i-1] + W[i+1],             k_m = dt^2 n_m^2
+//   p = 4: 16 (W[i-1] + W[i+1]) - (W[i-2] + W[i+2]),  k_m = dt^2 n_m^2 / 12
+// and kc = 2 sum k_m (p = 2) or 30 sum k_m (p = 4).
+struct StepGeom {
+  int dim;
+  int order;
+  int nx, ny, nz;      // cells per axis (nz = 0 in 2-D)
+  int64_t sy, sz;      // strides of the node arrays (x stride is 1)
+  int64_t nodes;       // (nx+1)(ny+1)(nz+1)
+  double kx, ky, kz, kc;
+  double c2const;      // used when the c2 pointer is null
+};
+
+enum FinalMode { ACCUMULATE = 0, FINAL_FILTER = 1, FINAL_A = 2 };
+
+// First step: W0 = v (walls 0), W1 = W0 + (1/2)(L W0 dt^2) + g0 f,
+// acc = w0 W0 + w1 W1.  c2/f may be null (constant c2 / no forcing).
+// `half` geometry has k_m and kc already halved.
+hipError_t launch_first_step(bool fp32, const StepGeom &half, const double *v, void *W0, void *W1,
+                             double *acc, const void *c2, const void *f, double g0, double w0,
+                             double w1, hipStream_t s);
+
+// One leapfrog step in place: prev_next holds W^{n-1} on entry, W^{n+1} on exit.
+// mode ACCUMULATE: acc += wn W^{n+1}; FINAL_FILTER: out = acc + wn W^{n+1};
+// FINAL_A: out = v - (acc + wn W^{n+1}).  Final modes also zero `out` on walls.
+hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev_next, double *acc,
+                       const void *c2, const void *f, double gn, double wn, int mode,
+                       const double *v, double *out, hipStream_t s);
+
+// Temporally blocked step: K leapfrog steps per pass over the grid for a
+// 2-D grid.  in_prev/in_cur hold W^{n-1}, W^n; out_prev/out_cur receive
+// W^{n+K-1}, W^{n+K}.  gn[j], wn[j] for j = 0..K-1 belong to the steps
+// producing W^{n+1+j}.  The last pass of an application uses mode != 0.
+struct BlockCoef {
+  double gn[8];
+  double wn[8];
+};
+hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int tile_x, int tile_y,
+                                 const void *in_prev, const void *in_cur, void *out_prev, void *out_cur,
+                                 double *acc, const void *c2, const void *f, const BlockCoef &coef,
+                                 int mode, const double *v, double *out, hipStream_t s);
+bool block_config_supported(bool fp32, int order, int K, int tile_x, int tile_y);
+
+// Convert/copy helpers.
+hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s);
+hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n, hipStream_t s);
+
+// Reductions (deterministic: fixed block count and fixed combine order).
+int reduction_blocks(int64_t n);
+// partials[i * nb + b] = block b's share of sum_e V_i[e] * w[e], i < k.
+hipError_t launch_mdot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partials,
+                       int nb, hipStream_t s);
+// out[i] = sum_b partials[i * nb + b] (block-tree order).
+hipError_t launch_reduce_rows(const double *partials, int nb, int k, double *out, hipStream_t s);
+// w[e] -= sum_i coef[i] * V_i[e]  (coef on device)
+hipError_t launch_block_axpy(const double *V, int64_t ldv, int k, const double *coef, double *w, int64_t n,
+                             hipStream_t s);
+// x[e] += sum_i coef[i] * V_i[e]  (coef on device)
+hipError_t launch_block_gemv_add(const double *V, int64_t ldv, int k, const double *coef, double *x,
+                                 int64_t n, hipStream_t s);
+// dst[e] = src[e] / sqrt(*norm2)
+hipError_t launch_scale_by_rnorm(const double *src, double *dst, const double *norm2, int64_t n,
+                                 hipStream_t s);
+// partials of sum (a - b)^2, then b = a
+hipError_t launch_diff_norm_copy(const double *a, double *b, int64_t n, double *partials, int nb,
+                                 hipStream_t s);
+// dst = a - b
+hipError_t launch_sub(const double *a, const double *b, double *dst, int64_t n, hipStream_t s);
+// partial min/max/non-finite count of src over interior nodes (3 * nb values)
+hipError_t launch_interior_stats(const StepGeom &g, const double *src, double *partials, int nb,
+                                 hipStream_t s);
+// res = c2 Delta u + omega^2 u - f (interior), 0 on walls; state precision FP64
+hipError_t launch_helmholtz_residual(const StepGeom &g_unscaled, const double *u, const void *c2, bool fp32_c2,
+                                     const void *f, bool fp32_f, double omega2, double *res, hipStream_t s);
+hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t s);
+
+}  // namespace wh

@@ -1,0 +1,483 @@
+// HIP kernels of the WaveHoltz hot path for CDNA4 (gfx950): the first step,
+// the fused leapfrog + filter step, and the FP64 reductions of the outer
+// solvers.  One node per thread; node arrays are dense, x fastest.
+//
+// The scheme is the explicit leapfrog of Sec. 4.2.1 (eq. WaveSchemeexplicit)
+// with the trapezoid filter of eq. (updateDiscreteExplicit) accumulated in FP64
+// as the steps are taken, so the time history is never stored.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wh_internal.h"
+
+namespace wh {
+namespace {
+
+constexpr int kBlockX = 64;
+constexpr int kBlockY = 4;
+constexpr int kRedThreads = 256;
+
+template <typename T>
+struct Coef {
+  T kx, ky, kz, kc;
+};
+
+// Value at a node index that may lie up to 2 nodes beyond a wall: odd
+// reflection u(-j) = -u(j), u(n+j) = -u(n-j).  Wall nodes themselves hold 0 in
+// every state array.
+template <typename T, int DIM>
+__device__ __forceinline__ T load_reflect(const T *__restrict__ W, int i, int j, int k,
+                                          const StepGeom &g) {
+  T s = T(1);
+  if (i < 0) { i = -i; s = -s; } else if (i > g.nx) { i = 2 * g.nx - i; s = -s; }
+  if (j < 0) { j = -j; s = -s; } else if (j > g.ny) { j = 2 * g.ny - j; s = -s; }
+  if (DIM == 3) {
+    if (k < 0) { k = -k; s = -s; } else if (k > g.nz) { k = 2 * g.nz - k; s = -s; }
+  }
+  return s * W[(int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz];
+}
+
+// sum_m k_m S_m(W) - kc W at an interior node (see StepGeom).
+template <typename T, int DIM, int P>
+__device__ __forceinline__ T stencil(const T *__restrict__ W, int i, int j, int k, int64_t idx,
+                                     const StepGeom &g, const Coef<T> &c) {
+  const T w0 = W[idx];
+  if (P == 2) {
+    // neighbours of an interior node are interior or wall nodes: no ghosts
+    T r = c.kx * (W[idx - 1] + W[idx + 1]) + c.ky * (W[idx - g.sy] + W[idx + g.sy]);
+    if (DIM == 3) r += c.kz * (W[idx - g.sz] + W[idx + g.sz]);
+    return r - c.kc * w0;
+  } else {
+    const bool near = (i < 2) || (i > g.nx - 2) || (j < 2) || (j > g.ny - 2) ||
+                      (DIM == 3 && ((k < 2) || (k > g.nz - 2)));
+    T ax1, ax2, ay1, ay2, az1 = T(0), az2 = T(0);
+    if (!near) {
+      ax1 = W[idx - 1] + W[idx + 1];
+      ax2 = W[idx - 2] + W[idx + 2];
+      ay1 = W[idx - g.sy] + W[idx + g.sy];
+      ay2 = W[idx - 2 * g.sy] + W[idx + 2 * g.sy];
+      if (DIM == 3) {
+        az1 = W[idx - g.sz] + W[idx + g.sz];
+        az2 = W[idx - 2 * g.sz] + W[idx + 2 * g.sz];
+      }
+    } else {
+      ax1 = load_reflect<T, DIM>(W, i - 1, j, k, g) + load_reflect<T, DIM>(W, i + 1, j, k, g);
+      ax2 = load_reflect<T, DIM>(W, i - 2, j, k, g) + load_reflect<T, DIM>(W, i + 2, j, k, g);
+      ay1 = load_reflect<T, DIM>(W, i, j - 1, k, g) + load_reflect<T, DIM>(W, i, j + 1, k, g);
+      ay2 = load_reflect<T, DIM>(W, i, j - 2, k, g) + load_reflect<T, DIM>(W, i, j + 2, k, g);
+      if (DIM == 3) {
+        az1 = load_reflect<T, DIM>(W, i, j, k - 1, g) + load_reflect<T, DIM>(W, i, j, k + 1, g);
+        az2 = load_reflect<T, DIM>(W, i, j, k - 2, g) + load_reflect<T, DIM>(W, i, j, k + 2, g);
+      }
+    }
+    T r = c.kx * (T(16) * ax1 - ax2) + c.ky * (T(16) * ay1 - ay2);
+    if (DIM == 3) r += c.kz * (T(16) * az1 - az2);
+    return r - c.kc * w0;
+  }
+}
+
+// Same stencil applied to a caller array whose wall values must be ignored
+// (treated as 0): used by the first step, which reads the iterate v directly.
+template <typename T, int DIM, int P>
+__device__ __forceinline__ T stencil_from_v(const double *__restrict__ v, int i, int j, int k,
+                                            const StepGeom &g, const Coef<T> &c) {
+  auto val = [&](int a, int b, int d) -> T {
+    T s = T(1);
+    if (a < 0) { a = -a; s = -s; } else if (a > g.nx) { a = 2 * g.nx - a; s = -s; }
+    if (b < 0) { b = -b; s = -s; } else if (b > g.ny) { b = 2 * g.ny - b; s = -s; }
+    if (DIM == 3) {
+      if (d < 0) { d = -d; s = -s; } else if (d > g.nz) { d = 2 * g.nz - d; s = -s; }
+    }
+    const bool wall = a == 0 || a == g.nx || b == 0 || b == g.ny || (DIM == 3 && (d == 0 || d == g.nz));
+    if (wall) return T(0);
+    return s * static_cast<T>(v[(int64_t)a + (int64_t)b * g.sy + (int64_t)d * g.sz]);
+  };
+  const T w0 = val(i, j, k);
+  if (P == 2) {
+    T r = c.kx * (val(i - 1, j, k) + val(i + 1, j, k)) + c.ky * (val(i, j - 1, k) + val(i, j + 1, k));
+    if (DIM == 3) r += c.kz * (val(i, j, k - 1) + val(i, j, k + 1));
+    return r - c.kc * w0;
+  } else {
+    T r = c.kx * (T(16) * (val(i - 1, j, k) + val(i + 1, j, k)) - (val(i - 2, j, k) + val(i + 2, j, k))) +
+          c.ky * (T(16) * (val(i, j - 1, k) + val(i, j + 1, k)) - (val(i, j - 2, k) + val(i, j + 2, k)));
+    if (DIM == 3)
+      r += c.kz * (T(16) * (val(i, j, k - 1) + val(i, j, k + 1)) - (val(i, j, k - 2) + val(i, j, k + 2)));
+    return r - c.kc * w0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ Coef<T> coef_of(const StepGeom &g) {
+  return Coef<T>{static_cast<T>(g.kx), static_cast<T>(g.ky), static_cast<T>(g.kz), static_cast<T>(g.kc)};
+}
+
+template <typename T, int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
+    StepGeom g, const double *__restrict__ v, T *__restrict__ W0, T *__restrict__ W1,
+    double *__restrict__ acc, const T *__restrict__ c2, const T *__restrict__ f, double g0, double w0,
+    double w1) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+  const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
+  if (wall) {
+    W0[idx] = T(0);
+    W1[idx] = T(0);
+    acc[idx] = 0.0;
+    return;
+  }
+  const Coef<T> c = coef_of<T>(g);
+  const T u0 = static_cast<T>(v[idx]);
+  const T c2v = c2 ? c2[idx] : static_cast<T>(g.c2const);
+  T u1 = u0 + c2v * stencil_from_v<T, DIM, P>(v, i, j, k, g, c);
+  if (f) u1 += static_cast<T>(g0) * f[idx];
+  W0[idx] = u0;
+  W1[idx] = u1;
+  acc[idx] = w0 * static_cast<double>(u0) + w1 * static_cast<double>(u1);
+}
+
+template <typename T, int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void step_kernel(
+    StepGeom g, const T *__restrict__ cur, T *__restrict__ prev_next, double *__restrict__ acc,
+    const T *__restrict__ c2, const T *__restrict__ f, double gn, double wn, int mode,
+    const double *__restrict__ v, double *__restrict__ out) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+  const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
+  if (wall) {
+    if (mode != ACCUMULATE) out[idx] = 0.0;
+    return;
+  }
+  const Coef<T> c = coef_of<T>(g);
+  const T c2v = c2 ? c2[idx] : static_cast<T>(g.c2const);
+  const T lap = stencil<T, DIM, P>(cur, i, j, k, idx, g, c);
+  T nxt = T(2) * cur[idx] - prev_next[idx] + c2v * lap;
+  if (f) nxt += static_cast<T>(gn) * f[idx];
+  prev_next[idx] = nxt;
+  const double a = acc[idx] + wn * static_cast<double>(nxt);
+  if (mode == ACCUMULATE) {
+    acc[idx] = a;
+  } else if (mode == FINAL_FILTER) {
+    out[idx] = a;
+  } else {
+    out[idx] = v[idx] - a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void to_state_kernel(const double *__restrict__ src, T *__restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = static_cast<T>(src[e]);
+}
+
+template <typename T>
+__global__ void from_state_kernel(const T *__restrict__ src, double *__restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = static_cast<double>(src[e]);
+}
+
+__global__ void fill_kernel(double *__restrict__ dst, double value, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = value;
+}
+
+// ---------------------------------------------------------------------------
+// reductions: wavefront shuffle tree, then the 4 wave results in fixed order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ double block_sum(double x, double *sm) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[wave] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+  return r;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kRedThreads) void mdot_kernel(const double *__restrict__ V, int64_t ldv,
+                                                           const double *__restrict__ w, int64_t n,
+                                                           double *__restrict__ partials, int nb) {
+  __shared__ double sm[4];
+  const int vec = blockIdx.y;
+  const double *x = V + (int64_t)vec * ldv;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += (int64_t)nb * kRedThreads)
+    s += x[e] * w[e];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) partials[(int64_t)vec * nb + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double *__restrict__ partials, int nb,
+                                                                  double *__restrict__ out) {
+  __shared__ double sm[4];
+  const double *row = partials + (int64_t)blockIdx.x * nb;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) s += row[b];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ void block_axpy_kernel(const double *__restrict__ V, int64_t ldv, int k, const double *__restrict__ coef,
+                                  double *__restrict__ w, int64_t n, double sign) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += coef[i] * V[(int64_t)i * ldv + e];
+    w[e] += sign * s;
+  }
+}
+
+__global__ void scale_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                             const double *__restrict__ norm2, int64_t n) {
+  const double r = 1.0 / sqrt(*norm2);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e] * r;
+}
+
+__global__ __launch_bounds__(kRedThreads) void diff_norm_copy_kernel(const double *__restrict__ a,
+                                                                     double *__restrict__ b, int64_t n,
+                                                                     double *__restrict__ partials, int nb) {
+  __shared__ double sm[4];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += (int64_t)nb * kRedThreads) {
+    const double d = a[e] - b[e];
+    s += d * d;
+    b[e] = a[e];
+  }
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void sub_kernel(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ dst,
+                           int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = a[e] - b[e];
+}
+
+__global__ __launch_bounds__(kRedThreads) void interior_stats_kernel(StepGeom g, const double *__restrict__ src,
+                                                                     double *__restrict__ partials, int nb) {
+  __shared__ double smx[kRedThreads], smn[kRedThreads], sbad[kRedThreads];
+  double mx = -__builtin_huge_val(), mn = __builtin_huge_val(), bad = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < g.nodes; e += (int64_t)nb * kRedThreads) {
+    const int64_t i = e % g.sy;
+    const int64_t j = (e / g.sy) % (g.ny + 1);
+    const int64_t k = (g.dim == 3) ? e / g.sz : 0;
+    const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (g.dim == 3 && (k == 0 || k == g.nz));
+    if (wall) continue;
+    const double x = src[e];
+    if (!(x == x) || x == __builtin_huge_val() || x == -__builtin_huge_val()) bad += 1.0;
+    else {
+      mx = x > mx ? x : mx;
+      mn = x < mn ? x : mn;
+    }
+  }
+  smx[threadIdx.x] = mx;
+  smn[threadIdx.x] = mn;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smx[threadIdx.x] = smx[threadIdx.x] > smx[threadIdx.x + w] ? smx[threadIdx.x] : smx[threadIdx.x + w];
+      smn[threadIdx.x] = smn[threadIdx.x] < smn[threadIdx.x + w] ? smn[threadIdx.x] : smn[threadIdx.x + w];
+      sbad[threadIdx.x] += sbad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = smx[0];
+    partials[3 * blockIdx.x + 1] = smn[0];
+    partials[3 * blockIdx.x + 2] = sbad[0];
+  }
+}
+
+template <typename TC, typename TF, int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void helmholtz_residual_kernel(
+    StepGeom g, const double *__restrict__ u, const TC *__restrict__ c2, const TF *__restrict__ f, double omega2,
+    double *__restrict__ res) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+  const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
+  if (wall) {
+    res[idx] = 0.0;
+    return;
+  }
+  const Coef<double> c = coef_of<double>(g);
+  const double c2v = c2 ? static_cast<double>(c2[idx]) : g.c2const;
+  const double lap = stencil_from_v<double, DIM, P>(u, i, j, k, g, c);
+  const double fv = f ? static_cast<double>(f[idx]) : 0.0;
+  res[idx] = c2v * lap + omega2 * u[idx] - fv;
+}
+
+dim3 node_grid(const StepGeom &g) {
+  return dim3((unsigned)((g.nx + 1 + kBlockX - 1) / kBlockX), (unsigned)((g.ny + 1 + kBlockY - 1) / kBlockY),
+              (unsigned)(g.dim == 3 ? g.nz + 1 : 1));
+}
+
+unsigned flat_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <typename T, int DIM, int P>
+void first_step_typed(const StepGeom &g, const double *v, void *W0, void *W1, double *acc, const void *c2,
+                      const void *f, double g0, double w0, double w1, hipStream_t s) {
+  first_step_kernel<T, DIM, P><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(
+      g, v, static_cast<T *>(W0), static_cast<T *>(W1), acc, static_cast<const T *>(c2),
+      static_cast<const T *>(f), g0, w0, w1);
+}
+
+template <typename T, int DIM, int P>
+void step_typed(const StepGeom &g, const void *cur, void *prev_next, double *acc, const void *c2, const void *f,
+                double gn, double wn, int mode, const double *v, double *out, hipStream_t s) {
+  step_kernel<T, DIM, P><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(
+      g, static_cast<const T *>(cur), static_cast<T *>(prev_next), acc, static_cast<const T *>(c2),
+      static_cast<const T *>(f), gn, wn, mode, v, out);
+}
+
+template <typename T>
+void dispatch_first(const StepGeom &g, const double *v, void *W0, void *W1, double *acc, const void *c2,
+                    const void *f, double g0, double w0, double w1, hipStream_t s) {
+  if (g.dim == 2 && g.order == 2) first_step_typed<T, 2, 2>(g, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+  else if (g.dim == 2) first_step_typed<T, 2, 4>(g, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+  else if (g.order == 2) first_step_typed<T, 3, 2>(g, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+  else first_step_typed<T, 3, 4>(g, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+}
+
+template <typename T>
+void dispatch_step(const StepGeom &g, const void *cur, void *prev_next, double *acc, const void *c2, const void *f,
+                   double gn, double wn, int mode, const double *v, double *out, hipStream_t s) {
+  if (g.dim == 2 && g.order == 2) step_typed<T, 2, 2>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  else if (g.dim == 2) step_typed<T, 2, 4>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  else if (g.order == 2) step_typed<T, 3, 2>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  else step_typed<T, 3, 4>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+}
+
+}  // namespace
+
+hipError_t launch_first_step(bool fp32, const StepGeom &half, const double *v, void *W0, void *W1, double *acc,
+                             const void *c2, const void *f, double g0, double w0, double w1, hipStream_t s) {
+  if (fp32) dispatch_first<float>(half, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+  else dispatch_first<double>(half, v, W0, W1, acc, c2, f, g0, w0, w1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev_next, double *acc, const void *c2,
+                       const void *f, double gn, double wn, int mode, const double *v, double *out,
+                       hipStream_t s) {
+  if (fp32) dispatch_step<float>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  else dispatch_step<double>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s) {
+  if (fp32) to_state_kernel<float><<<flat_blocks(n), 256, 0, s>>>(src, static_cast<float *>(dst), n);
+  else to_state_kernel<double><<<flat_blocks(n), 256, 0, s>>>(src, static_cast<double *>(dst), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n, hipStream_t s) {
+  if (fp32) from_state_kernel<float><<<flat_blocks(n), 256, 0, s>>>(static_cast<const float *>(src), dst, n);
+  else from_state_kernel<double><<<flat_blocks(n), 256, 0, s>>>(static_cast<const double *>(src), dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t s) {
+  fill_kernel<<<flat_blocks(n), 256, 0, s>>>(dst, value, n);
+  return hipGetLastError();
+}
+
+int reduction_blocks(int64_t n) {
+  int64_t b = (n + 4 * kRedThreads - 1) / (4 * kRedThreads);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_mdot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partials, int nb,
+                       hipStream_t s) {
+  mdot_kernel<<<dim3((unsigned)nb, (unsigned)k), kRedThreads, 0, s>>>(V, ldv, w, n, partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double *partials, int nb, int k, double *out, hipStream_t s) {
+  reduce_rows_kernel<<<(unsigned)k, kRedThreads, 0, s>>>(partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_axpy(const double *V, int64_t ldv, int k, const double *coef, double *w, int64_t n,
+                             hipStream_t s) {
+  block_axpy_kernel<<<flat_blocks(n), 256, 0, s>>>(V, ldv, k, coef, w, n, -1.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_gemv_add(const double *V, int64_t ldv, int k, const double *coef, double *x, int64_t n,
+                                 hipStream_t s) {
+  block_axpy_kernel<<<flat_blocks(n), 256, 0, s>>>(V, ldv, k, coef, x, n, 1.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_by_rnorm(const double *src, double *dst, const double *norm2, int64_t n, hipStream_t s) {
+  scale_kernel<<<flat_blocks(n), 256, 0, s>>>(src, dst, norm2, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff_norm_copy(const double *a, double *b, int64_t n, double *partials, int nb, hipStream_t s) {
+  diff_norm_copy_kernel<<<(unsigned)nb, kRedThreads, 0, s>>>(a, b, n, partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(const double *a, const double *b, double *dst, int64_t n, hipStream_t s) {
+  sub_kernel<<<flat_blocks(n), 256, 0, s>>>(a, b, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_interior_stats(const StepGeom &g, const double *src, double *partials, int nb, hipStream_t s) {
+  interior_stats_kernel<<<(unsigned)nb, kRedThreads, 0, s>>>(g, src, partials, nb);
+  return hipGetLastError();
+}
+
+template <typename TC, typename TF>
+static void residual_typed(const StepGeom &g, const double *u, const void *c2, const void *f, double omega2,
+                           double *res, hipStream_t s) {
+  const TC *c = static_cast<const TC *>(c2);
+  const TF *ff = static_cast<const TF *>(f);
+  if (g.dim == 2 && g.order == 2)
+    helmholtz_residual_kernel<TC, TF, 2, 2><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(g, u, c, ff, omega2, res);
+  else if (g.dim == 2)
+    helmholtz_residual_kernel<TC, TF, 2, 4><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(g, u, c, ff, omega2, res);
+  else if (g.order == 2)
+    helmholtz_residual_kernel<TC, TF, 3, 2><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(g, u, c, ff, omega2, res);
+  else
+    helmholtz_residual_kernel<TC, TF, 3, 4><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(g, u, c, ff, omega2, res);
+}
+
+hipError_t launch_helmholtz_residual(const StepGeom &g, const double *u, const void *c2, bool fp32_c2, const void *f,
+                                     bool fp32_f, double omega2, double *res, hipStream_t s) {
+  if (fp32_c2 && fp32_f) residual_typed<float, float>(g, u, c2, f, omega2, res, s);
+  else if (fp32_c2) residual_typed<float, double>(g, u, c2, f, omega2, res, s);
+  else if (fp32_f) residual_typed<double, float>(g, u, c2, f, omega2, res, s);
+  else residual_typed<double, double>(g, u, c2, f, omega2, res, s);
+  return hipGetLastError();
+}
+
+}  // namespace wh

@@ -1,0 +1,403 @@
+"""Python binding of the WaveHoltz C ABI (``include/wh.h``).
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls and every step of the computation runs in ``libwh.so``'s HIP
+kernels.  PyTorch supplies device memory (the workspace and the grid
+functions) and the stream.  If the HIP library is missing the import fails;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwh.so")
+
+WH_OK, WH_EINVAL, WH_ENOMEM, WH_EDEVICE, WH_EUNSTABLE, WH_ENOTCONV, WH_ENONFINITE, WH_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+WH_FP64, WH_FP32_STATE = 0, 1
+WH_SOLVER_FPI, WH_SOLVER_GMRES = 0, 1
+WH_MAX_RESTART = 256
+
+
+class WhError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_name(status)} ({status}): {message}")
+        self.status = status
+
+
+class wh_time_params(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("periods", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("omega", ctypes.c_double), ("omega_e", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("c2max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+WH_ITER_CALLBACK = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p)
+
+
+class wh_solve_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("rtol", ctypes.c_double), ("on_iter", WH_ITER_CALLBACK),
+                ("user", ctypes.c_void_p)]
+
+
+class wh_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("applies", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("scaled_res", ctypes.c_double), ("cr_last", ctypes.c_double), ("cr_avg", ctypes.c_double),
+                ("ecr", ctypes.c_double), ("mu_pred", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("point_steps", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class wh_profile(ctypes.Structure):
+    _fields_ = [("applies", ctypes.c_int64), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("point_steps", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_I64x3 = ctypes.c_int64 * 3
+_vp = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run `python -m paper_2504_03074_amd.build`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "wh_version": (ctypes.c_int32, []),
+        "wh_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+        "wh_compute_time_params": (st, [ctypes.c_int32, _I64x3, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.POINTER(wh_time_params)]),
+        "wh_create": (st, [ctypes.POINTER(_vp), ctypes.c_int32, _vp]),
+        "wh_destroy": (None, [_vp]),
+        "wh_last_error": (ctypes.c_char_p, [_vp]),
+        "wh_set_grid": (st, [_vp, ctypes.c_int32, _I64x3, ctypes.c_int32, ctypes.c_int32]),
+        "wh_workspace_size": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+        "wh_bind_workspace": (st, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32]),
+        "wh_set_c2": (st, [_vp, _vp, ctypes.c_int32]),
+        "wh_set_c2_constant": (st, [_vp, ctypes.c_double]),
+        "wh_set_source": (st, [_vp, _vp, ctypes.c_int32]),
+        "wh_set_frequency": (st, [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.c_double]),
+        "wh_get_time_params": (st, [_vp, ctypes.POINTER(wh_time_params)]),
+        "wh_run_periods": (st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
+        "wh_apply": (st, [_vp, _vp, _vp, ctypes.c_int32]),
+        "wh_apply_A": (st, [_vp, _vp, _vp]),
+        "wh_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, ctypes.POINTER(wh_solve_info)]),
+        "wh_helmholtz_residual": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "wh_dot": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "wh_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "wh_get_tuning": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32)]),
+        "wh_profile_enable": (st, [_vp, ctypes.c_int32]),
+        "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises ImportError if it was not built)."""
+    return _load()
+
+
+def status_name(status: int) -> str:
+    return _load().wh_status_string(int(status)).decode()
+
+
+def _check(ctx, status):
+    if status != WH_OK:
+        msg = _load().wh_last_error(ctx).decode() if ctx else ""
+        raise WhError(status, msg)
+
+
+def _n3(n):
+    n = list(int(x) for x in n) + [0] * (3 - len(n))
+    return _I64x3(*n[:3])
+
+
+# --------------------------------------------------------------------------
+# thin wrappers, one per C entry point
+# --------------------------------------------------------------------------
+def wh_version() -> int:
+    return int(_load().wh_version())
+
+
+def wh_status_string(status: int) -> str:
+    return status_name(status)
+
+
+def wh_compute_time_params(dim, n, order, c2max, omega, periods=1, cfl_frac=0.9, nt_override=0,
+                           alpha=-1.0) -> wh_time_params:
+    out = wh_time_params()
+    st = _load().wh_compute_time_params(int(dim), _n3(n), int(order), float(c2max), float(omega), int(periods),
+                                        float(cfl_frac), int(nt_override), float(alpha), ctypes.byref(out))
+    if st != WH_OK:
+        raise WhError(st, "wh_compute_time_params rejected its arguments")
+    return out
+
+
+def wh_create(device: int = 0, stream: int | None = None):
+    ctx = _vp()
+    st = _load().wh_create(ctypes.byref(ctx), int(device), _vp(stream) if stream else None)
+    if st != WH_OK:
+        raise WhError(st, f"wh_create(device={device}) failed")
+    return ctx
+
+
+def wh_destroy(ctx):
+    _load().wh_destroy(ctx)
+
+
+def wh_last_error(ctx) -> str:
+    return _load().wh_last_error(ctx).decode()
+
+
+def wh_set_grid(ctx, dim, n, order, precision=WH_FP64):
+    _check(ctx, _load().wh_set_grid(ctx, int(dim), _n3(n), int(order), int(precision)))
+
+
+def wh_workspace_size(ctx, restart=0) -> int:
+    out = ctypes.c_size_t()
+    _check(ctx, _load().wh_workspace_size(ctx, int(restart), ctypes.byref(out)))
+    return int(out.value)
+
+
+def wh_bind_workspace(ctx, ptr: int, nbytes: int, restart=0):
+    _check(ctx, _load().wh_bind_workspace(ctx, _vp(ptr), int(nbytes), int(restart)))
+
+
+def wh_set_c2(ctx, ptr: int | None, on_device: bool):
+    _check(ctx, _load().wh_set_c2(ctx, _vp(ptr) if ptr else None, int(bool(on_device))))
+
+
+def wh_set_c2_constant(ctx, c2: float):
+    _check(ctx, _load().wh_set_c2_constant(ctx, float(c2)))
+
+
+def wh_set_source(ctx, ptr: int, on_device: bool):
+    _check(ctx, _load().wh_set_source(ctx, _vp(ptr), int(bool(on_device))))
+
+
+def wh_set_frequency(ctx, omega, periods=1, cfl_frac=0.9, nt_override=0, alpha=-1.0):
+    _check(ctx, _load().wh_set_frequency(ctx, float(omega), int(periods), float(cfl_frac), int(nt_override),
+                                         float(alpha)))
+
+
+def wh_get_time_params(ctx) -> wh_time_params:
+    out = wh_time_params()
+    _check(ctx, _load().wh_get_time_params(ctx, ctypes.byref(out)))
+    return out
+
+
+def wh_run_periods(ctx, w0: int, with_forcing: bool, w_final: int | None, filtered: int | None):
+    _check(ctx, _load().wh_run_periods(ctx, _vp(w0), int(bool(with_forcing)), _vp(w_final) if w_final else None,
+                                       _vp(filtered) if filtered else None))
+
+
+def wh_apply(ctx, v: int, out: int, with_forcing: bool):
+    _check(ctx, _load().wh_apply(ctx, _vp(v), _vp(out), int(bool(with_forcing))))
+
+
+def wh_apply_A(ctx, v: int, Av: int):
+    _check(ctx, _load().wh_apply_A(ctx, _vp(v), _vp(Av)))
+
+
+def wh_solve(ctx, opts: wh_solve_opts, v: int) -> tuple[int, wh_solve_info]:
+    """Returns (status, info); WH_ENOTCONV is returned, not raised, so the
+    caller can inspect the last iterate."""
+    info = wh_solve_info()
+    st = _load().wh_solve(ctx, ctypes.byref(opts), _vp(v), ctypes.byref(info))
+    if st not in (WH_OK, WH_ENOTCONV):
+        _check(ctx, st)
+    return st, info
+
+
+def wh_helmholtz_residual(ctx, u: int, res: int | None) -> float:
+    rel = ctypes.c_double()
+    _check(ctx, _load().wh_helmholtz_residual(ctx, _vp(u), _vp(res) if res else None, ctypes.byref(rel)))
+    return float(rel.value)
+
+
+def wh_dot(ctx, x: int, y: int) -> float:
+    out = ctypes.c_double()
+    _check(ctx, _load().wh_dot(ctx, _vp(x), _vp(y), ctypes.byref(out)))
+    return float(out.value)
+
+
+def wh_set_tuning(ctx, kblock=0, tile_x=0, tile_y=0):
+    _check(ctx, _load().wh_set_tuning(ctx, int(kblock), int(tile_x), int(tile_y)))
+
+
+def wh_get_tuning(ctx):
+    k, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, _load().wh_get_tuning(ctx, ctypes.byref(k), ctypes.byref(tx), ctypes.byref(ty)))
+    return int(k.value), int(tx.value), int(ty.value)
+
+
+def wh_profile_enable(ctx, enable=True):
+    _check(ctx, _load().wh_profile_enable(ctx, int(bool(enable))))
+
+
+def wh_profile_read(ctx) -> wh_profile:
+    out = wh_profile()
+    _check(ctx, _load().wh_profile_read(ctx, ctypes.byref(out)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# convenience object over torch tensors
+# --------------------------------------------------------------------------
+class Solver:
+    """One WaveHoltz problem on one GPU, with torch-owned device memory.
+
+    Grid functions are float64 torch tensors of node shape
+    (n_y+1, n_x+1) or (n_z+1, n_y+1, n_x+1) on the solver's device.
+    """
+
+    def __init__(self, dim, n, order=2, precision="fp64", restart=0, device=0, stream=None):
+        import torch
+        self._torch = torch
+        if isinstance(n, int):
+            n = (n,) * dim
+        self.dim, self.n, self.order = int(dim), tuple(int(x) for x in n), int(order)
+        self.precision = WH_FP32_STATE if precision in ("fp32", WH_FP32_STATE) else WH_FP64
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = wh_create(device, self.stream.cuda_stream)
+        wh_set_grid(self.ctx, self.dim, self.n, self.order, self.precision)
+        self.restart = int(restart)
+        nbytes = wh_workspace_size(self.ctx, self.restart)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        wh_bind_workspace(self.ctx, self.workspace.data_ptr(), nbytes, self.restart)
+        self._keep = []
+
+    @property
+    def shape(self):
+        return tuple(k + 1 for k in reversed(self.n))
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                wh_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    def _dev(self, a, name):
+        t = self._torch
+        if not isinstance(a, t.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if a.dtype != t.float64 or tuple(a.shape) != self.shape or not a.is_contiguous() or a.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {self.shape} on {self.device}")
+        return a.data_ptr()
+
+    def _any(self, a, name):
+        """(pointer, on_device, keepalive) for a torch tensor or numpy array."""
+        t = self._torch
+        if isinstance(a, t.Tensor):
+            if a.device.type == "cuda":
+                return self._dev(a, name), True, a
+            a = a.detach().numpy()
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != self.shape:
+            raise ValueError(f"{name} must have shape {self.shape}")
+        return a.ctypes.data, False, a
+
+    def new(self):
+        return self._torch.zeros(self.shape, dtype=self._torch.float64, device=self.device)
+
+    def set_c2(self, c2):
+        if isinstance(c2, (int, float)):
+            wh_set_c2_constant(self.ctx, float(c2))
+        else:
+            ptr, on_dev, keep = self._any(c2, "c2")
+            wh_set_c2(self.ctx, ptr, on_dev)
+
+    def set_source(self, f):
+        ptr, on_dev, keep = self._any(f, "f")
+        wh_set_source(self.ctx, ptr, on_dev)
+
+    def set_frequency(self, omega, periods=1, cfl_frac=0.9, nt=0, alpha=-1.0):
+        wh_set_frequency(self.ctx, omega, periods, cfl_frac, nt, alpha)
+        return self.time_params
+
+    @property
+    def time_params(self):
+        return wh_get_time_params(self.ctx).as_dict()
+
+    def set_tuning(self, kblock=0, tile_x=0, tile_y=0):
+        wh_set_tuning(self.ctx, kblock, tile_x, tile_y)
+
+    def tuning(self):
+        return wh_get_tuning(self.ctx)
+
+    def apply(self, v, with_forcing=True, out=None):
+        out = self.new() if out is None else out
+        wh_apply(self.ctx, self._dev(v, "v"), self._dev(out, "out"), with_forcing)
+        return out
+
+    def apply_A(self, v, out=None):
+        out = self.new() if out is None else out
+        wh_apply_A(self.ctx, self._dev(v, "v"), self._dev(out, "out"))
+        return out
+
+    def run_periods(self, w0, with_forcing=True, want_final=True, want_filtered=True):
+        fin = self.new() if want_final else None
+        fil = self.new() if want_filtered else None
+        wh_run_periods(self.ctx, self._dev(w0, "w0"), with_forcing, fin.data_ptr() if fin is not None else None,
+                       fil.data_ptr() if fil is not None else None)
+        return fin, fil
+
+    def solve(self, method="gmres", rtol=1e-8, maxit=1000, restart=None, v0=None, callback=None):
+        v = self.new() if v0 is None else v0.clone()
+        opts = wh_solve_opts()
+        opts.method = WH_SOLVER_GMRES if method == "gmres" else WH_SOLVER_FPI
+        opts.restart = int(self.restart if restart is None else restart)
+        opts.maxit = int(maxit)
+        opts.flags = 0
+        opts.rtol = float(rtol)
+        cb = None
+        if callback is not None:
+            cb = WH_ITER_CALLBACK(lambda k, r, u: callback(k, r))
+            opts.on_iter = cb
+        opts.user = None
+        st, info = wh_solve(self.ctx, opts, self._dev(v, "v"))
+        d = info.as_dict()
+        d["converged"] = st == WH_OK
+        return v, d
+
+    def helmholtz_residual(self, u, want_field=False):
+        res = self.new() if want_field else None
+        rel = wh_helmholtz_residual(self.ctx, self._dev(u, "u"), res.data_ptr() if res is not None else None)
+        return (rel, res) if want_field else rel
+
+    def dot(self, x, y):
+        return wh_dot(self.ctx, self._dev(x, "x"), self._dev(y, "y"))
+
+    def profile_enable(self, enable=True):
+        wh_profile_enable(self.ctx, enable)
+
+    def profile_read(self):
+        return wh_profile_read(self.ctx).as_dict()

@@ -1,0 +1,354 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Every case feeds the same seeded inputs (``workloads``) to both sides.
+Bars: relative L2 <= 1e-11 in FP64 and <= 1e-5 with FP32 state; wall nodes
+must be exactly 0.  Small cases are compared element by element; the
+full-size configurations on sampled outputs (each computed by the oracle on
+its domain of dependence) and on closed-form sine modes.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as cf
+from oracle import core as oc
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-11, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a GPU: the HIP path has no CPU fallback")
+    return _t
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(dim, n, order, prec, restart=0):
+    from paper_2504_03074_amd import Solver
+    return Solver(dim, n, order=order, precision=prec, restart=restart)
+
+
+def _to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _walls_zero(a):
+    m = np.ones(a.shape, dtype=bool)
+    m[(slice(1, -1),) * a.ndim] = False
+    return bool(np.all(a[m] == 0.0))
+
+
+def _problem(dim, n, order, c2kind, seed):
+    grid = oc.Grid(dim, n, order)
+    if c2kind == "const":
+        c2 = 1.3
+    else:
+        g = wl.random_field(grid.shape, seed=seed, zero_walls=False)
+        c2 = 0.6 + 1.2 / (1.0 + np.exp(-g))  # in (0.6, 1.8), rough on purpose
+    f = wl.random_field(grid.shape, seed=seed + 1)
+    v = wl.random_field(grid.shape, seed=seed + 2)
+    return grid, c2, f, v
+
+
+APPLY_CASES = [
+    # dim, n, order, c2kind, periods, omega
+    (2, (61, 47), 2, "const", 1, 25.0),
+    (2, (61, 47), 4, "var", 1, 25.0),
+    (2, (61, 47), 4, "const", 2, 19.0),
+    (2, (130, 67), 2, "var", 1, 41.0),
+    (3, (21, 18, 15), 2, "var", 1, 12.0),
+    (3, (21, 18, 15), 4, "const", 1, 12.0),
+    (3, (17, 23, 12), 4, "var", 2, 9.5),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,order,c2kind,periods,omega", APPLY_CASES)
+def test_apply_and_apply_A(torch, prec, dim, n, order, c2kind, periods, omega):
+    _say(f"[apply] dim={dim} n={n} p={order} c2={c2kind} Np={periods} omega={omega} {prec}")
+    grid, c2, f, v = _problem(dim, n, order, c2kind, seed=100 + dim * 10 + order)
+    s = _solver(dim, n, order, prec)
+    s.set_c2(c2)
+    s.set_source(f)
+    tp_gpu = s.set_frequency(omega, periods=periods)
+    tp = oc.time_params(grid, c2, omega, periods=periods)
+    assert tp_gpu["nt"] == tp["nt"]
+    vd = _to_dev(torch, v)
+    got = s.apply(vd, with_forcing=True).cpu().numpy()
+    want = oc.apply(grid, c2, f, v, tp, with_forcing=True)
+    assert _rel(got, want) <= TOL[prec]
+    assert _walls_zero(got)
+    gotA = s.apply_A(vd).cpu().numpy()
+    wantA = oc.apply_A(grid, c2, v, tp)
+    assert _rel(gotA, wantA) <= TOL[prec]
+    assert _walls_zero(gotA)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_run_periods_final_state_and_filter(torch, prec):
+    _say(f"[run_periods] {prec}")
+    grid, c2, f, v = _problem(2, (45, 52), 4, "var", seed=7)
+    s = _solver(2, (45, 52), 4, prec)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(17.0)
+    tp = oc.time_params(grid, c2, 17.0)
+    fin, fil = s.run_periods(_to_dev(torch, v), with_forcing=True)
+    want_fil, want_fin = oc.apply(grid, c2, f, v, tp, return_final=True)
+    assert _rel(fil.cpu().numpy(), want_fil) <= TOL[prec]
+    assert _rel(fin.cpu().numpy(), want_fin) <= TOL[prec]
+
+
+def test_wall_values_of_inputs_are_ignored(torch):
+    _say("[walls ignored]")
+    grid, c2, f, v = _problem(2, (33, 29), 4, "var", seed=9)
+    s = _solver(2, (33, 29), 4, "fp64")
+    s.set_c2(c2)
+    noisy_f = f.copy()
+    noisy_f[0, :] = 5.0
+    noisy_f[:, -1] = -3.0
+    s.set_source(noisy_f)
+    s.set_frequency(14.0)
+    noisy_v = v.copy()
+    noisy_v[-1, :] = 7.0
+    noisy_v[:, 0] = 2.0
+    tp = oc.time_params(grid, c2, 14.0)
+    got = s.apply(_to_dev(torch, noisy_v)).cpu().numpy()
+    want = oc.apply(grid, c2, f, v, tp)
+    assert _rel(got, want) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,order,ks", [(2, (64, 48), 4, (3, 5)), (3, (20, 24, 16), 2, (1, 2, 3)),
+                                            (2, (2048, 2048), 4, (101, 97))])
+def test_sine_mode_gives_beta_d(torch, prec, dim, n, order, ks):
+    """W_h(mode, 0) = beta_d(lambda~) mode (closed form, Sec. 4.2.1)."""
+    _say(f"[eigenmode] dim={dim} n={n} p={order} ks={ks} {prec}")
+    grid = oc.Grid(dim, n, order)
+    s = _solver(dim, n, order, prec)
+    s.set_c2(1.0)
+    s.set_source(np.zeros(grid.shape))
+    omega = 2.0 * math.pi * max(ks) * 0.93
+    s.set_frequency(omega)
+    tp = oc.time_params(grid, 1.0, omega)
+    xs = oc.coords(grid)
+    mode = np.ones(grid.shape)
+    for x, k in zip(xs, ks):
+        mode = mode * np.sin(k * math.pi * x)
+    lam2 = sum(cf.lambda_h_sq_1d(k * math.pi, 1.0 / nn, order) for k, nn in zip(ks, n))
+    beta = float(cf.beta_d_tp(cf.lambda_tilde(math.sqrt(lam2), tp["dt"]), tp))
+    got = s.apply(_to_dev(torch, mode), with_forcing=False).cpu().numpy()
+    err = np.abs(got - beta * mode).max()
+    assert err <= (1e-11 if prec == "fp64" else 1e-5), (beta, err)
+
+
+def test_fpi_single_gaussian_square_30_iterations(torch):
+    """128^2, 2nd order, c = 1, omega = 10.3, 30 fixed-point iterations (FP64)."""
+    _say("[fpi 128^2 x30]")
+    w = wl.single_gaussian_source()
+    grid = oc.Grid(2, (128, 128), 2)
+    s = _solver(2, (128, 128), 2, "fp64")
+    s.set_c2(1.0)
+    s.set_source(w["f"])
+    s.set_frequency(w["omega"])
+    v, info = s.solve(method="fpi", rtol=0.0, maxit=30)
+    tp = oc.time_params(grid, 1.0, w["omega"])
+    want, hist = oc.fpi(grid, 1.0, w["f"], tp, 30)
+    assert info["iters"] == 30 and info["applies"] == 30
+    assert _rel(v.cpu().numpy(), want) <= 1e-11
+    bnorm = hist[0]
+    assert info["bnorm"] == pytest.approx(bnorm, rel=1e-11)
+    assert info["rel_res"] == pytest.approx(hist[-1] / bnorm, rel=1e-9)
+    mu, _ = cf.predicted_rate(grid, 1.0, tp)
+    assert info["mu_pred"] == pytest.approx(mu, rel=1e-12)
+    # and against the closed form of the 30th iterate
+    ref = cf.fpi_iterate_closed_form(grid, 1.0, w["f"], w["omega"], tp, 30)
+    assert _rel(v.cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("restart,iters", [(50, 9), (3, 8)])
+def test_gmres_fixed_iteration_count(torch, restart, iters):
+    _say(f"[gmres fixed] restart={restart} iters={iters}")
+    grid, c2, f, _ = _problem(2, (40, 33), 4, "var", seed=31)
+    s = _solver(2, (40, 33), 4, "fp64", restart=restart)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(13.0)
+    tp = oc.time_params(grid, c2, 13.0)
+    x, info = s.solve(method="gmres", rtol=0.0, maxit=iters, restart=restart)
+    want, oinfo = oc.gmres(grid, c2, f, tp, restart=restart, fixed_iters=iters)
+    assert info["iters"] == iters
+    assert _rel(x.cpu().numpy(), want) <= 1e-11
+    assert info["rel_res"] == pytest.approx(oinfo["rel_res"], rel=1e-8)
+
+
+def _best_omega(grid, c2, candidates):
+    import scipy.sparse as sp
+    inner = (slice(1, -1),) * grid.dim
+    L = cf.laplacian_matrix(grid)
+    c2i = (np.full(grid.shape, c2) if np.isscalar(c2) else c2)[inner].ravel()
+    ev = np.linalg.eigvals((sp.diags(c2i) @ L).toarray())
+    lam = np.sqrt(np.maximum(-ev.real, 0))
+    best = None
+    for om in candidates:
+        tp = oc.time_params(grid, c2, om)
+        gap = float(np.min(np.abs(1 - cf.beta_d_tp(cf.lambda_tilde(lam, tp["dt"]), tp))))
+        if best is None or gap > best[1]:
+            best = (om, gap)
+    return best[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,order", [(2, (26, 21), 2), (2, (26, 21), 4), (3, (9, 8, 10), 4)])
+def test_gmres_converges_to_direct_solve(torch, prec, dim, n, order):
+    _say(f"[gmres converged] dim={dim} n={n} p={order} {prec}")
+    grid, c2, f, _ = _problem(dim, n, order, "var", seed=41)
+    omega = _best_omega(grid, c2, np.linspace(5.0, 15.0, 21))
+    s = _solver(dim, n, order, prec, restart=40)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(omega)
+    rtol = 1e-12 if prec == "fp64" else 1e-6
+    x, info = s.solve(method="gmres", rtol=rtol, maxit=2000, restart=40)
+    assert info["converged"], info
+    U = cf.dhs_direct(grid, c2, f, omega)
+    err = _rel(x.cpu().numpy(), U)
+    if prec == "fp64":
+        assert err <= 1e-9
+        assert s.helmholtz_residual(x) <= 1e-9
+    else:
+        # the FP32-state operator's fixed point differs from the FP64 one by O(kappa * eps_32)
+        assert err <= 1e-3
+
+
+def test_fpi_with_tolerance_reaches_closed_form(torch):
+    _say("[fpi rtol]")
+    grid = oc.Grid(2, (24, 24), 2)
+    f = wl.random_field(grid.shape, seed=5)
+    s = _solver(2, (24, 24), 2, "fp64")
+    s.set_c2(1.0)
+    s.set_source(f)
+    s.set_frequency(6.0)
+    x, info = s.solve(method="fpi", rtol=1e-12, maxit=5000)
+    assert info["converged"]
+    U = cf.helmholtz_closed_form(grid, 1.0, f, 6.0)
+    assert _rel(x.cpu().numpy(), U) <= 1e-10
+    # measured rate approaches the predicted one (Theorem 2)
+    assert info["cr_last"] == pytest.approx(info["mu_pred"], rel=2e-2)
+
+
+def test_helmholtz_residual_and_dot(torch):
+    _say("[residual, dot]")
+    grid, c2, f, u = _problem(3, (14, 11, 13), 4, "var", seed=51)
+    s = _solver(3, (14, 11, 13), 4, "fp64")
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(7.0)
+    ud = _to_dev(torch, u)
+    rel, res = s.helmholtz_residual(ud, want_field=True)
+    want = oc.helmholtz_residual(grid, c2, f, u, 7.0)
+    assert _rel(res.cpu().numpy(), want) <= 1e-13
+    assert rel == pytest.approx(np.linalg.norm(want) / np.linalg.norm(f), rel=1e-12)
+    assert s.dot(ud, ud) == pytest.approx(float(np.sum(u * u)), rel=1e-13)
+
+
+def test_repeat_runs_are_bitwise_identical(torch):
+    _say("[determinism]")
+    grid, c2, f, _ = _problem(2, (70, 55), 4, "var", seed=61)
+    s = _solver(2, (70, 55), 4, "fp64", restart=20)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(21.0)
+    x1, i1 = s.solve(method="gmres", rtol=0.0, maxit=25, restart=20)
+    x2, i2 = s.solve(method="gmres", rtol=0.0, maxit=25, restart=20)
+    assert torch.equal(x1, x2)
+    assert i1["rel_res"] == i2["rel_res"]
+
+
+def test_invariants_on_gpu(torch):
+    _say("[invariants]")
+    grid, c2, f, u = _problem(2, (48, 40), 4, "const", seed=71)
+    s = _solver(2, (48, 40), 4, "fp64")
+    s.set_c2(1.0)
+    s.set_source(f)
+    s.set_frequency(15.0)
+    ud = _to_dev(torch, u)
+    vd = _to_dev(torch, wl.random_field(grid.shape, seed=72))
+    z = torch.zeros_like(ud)
+    assert float(s.apply_A(z).abs().max()) == 0.0
+    Su, Sv = s.apply(ud, False), s.apply(vd, False)
+    assert s.dot(ud, Sv) == pytest.approx(s.dot(Su, vd), rel=1e-12)  # S symmetric for constant c
+    b = s.apply(z, True)
+    lhs = s.apply(ud, True)
+    assert float((lhs - (Su + b)).abs().max()) <= 1e-12 * float(lhs.abs().max())
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations: sampled outputs through the domain of dependence
+# ---------------------------------------------------------------------------
+SAMPLES_2D = [(1, 1), (2047, 2047), (3, 1500), (1024, 1024), (700, 2045), (1999, 12)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_speed_square_2048_sampled(torch, prec):
+    """2048^2, 4th order, random c^2 in [0.5, 2], omega = 200: W_h(v, f) and
+    A v at sampled nodes (corners, edges, centre) against the oracle."""
+    _say(f"[2048^2 sampled] {prec}")
+    w = wl.smooth_random_speed_sources()
+    grid = oc.Grid(2, (2048, 2048), 4)
+    s = _solver(2, (2048, 2048), 4, prec)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    s.set_frequency(w["omega"])
+    tp = oc.time_params(grid, w["c2"], w["omega"])
+    assert s.time_params["nt"] == tp["nt"]
+    v = wl.random_field(grid.shape, seed=2024)
+    vd = _to_dev(torch, v)
+    got = s.apply(vd, True).cpu().numpy()
+    gotA = s.apply_A(vd).cpu().numpy()
+    want = oc.apply_at_points(grid, w["c2"], w["f"], v, tp, SAMPLES_2D, with_forcing=True)
+    wantS = oc.apply_at_points(grid, w["c2"], None, v, tp, SAMPLES_2D, with_forcing=False)
+    g = np.array([got[p[1], p[0]] for p in SAMPLES_2D])
+    gA = np.array([gotA[p[1], p[0]] for p in SAMPLES_2D])
+    vs = np.array([v[p[1], p[0]] for p in SAMPLES_2D])
+    scale = np.abs(got).max()
+    tol = TOL[prec] * 10
+    assert np.abs(g - want).max() <= tol * scale
+    assert np.abs(gA - (vs - wantS)).max() <= tol * np.abs(gotA).max()
+    assert _walls_zero(got) and _walls_zero(gotA)
+
+
+def test_inclusion_cube_512_sampled_fp32(torch):
+    """512^3, 2nd order, c = 1 with a c = 1.5 ball, omega = 80, FP32 state:
+    W_h(v, f) at nodes near a corner and an edge against the oracle."""
+    _say("[512^3 sampled] fp32 p=2")
+    w = wl.cube_inclusion(n=512, order=2)
+    grid = oc.Grid(3, (512, 512, 512), 2)
+    s = _solver(3, (512, 512, 512), 2, "fp32")
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    s.set_frequency(w["omega"])
+    tp = oc.time_params(grid, w["c2"], w["omega"])
+    assert s.time_params["nt"] == tp["nt"]
+    v = wl.random_field(grid.shape, seed=333)
+    got = s.apply(_to_dev(torch, v), True).cpu().numpy()
+    pts = [(2, 3, 1), (509, 1, 510)]
+    want = oc.apply_at_points(grid, w["c2"], w["f"], v, tp, pts, with_forcing=True)
+    g = np.array([got[p[2], p[1], p[0]] for p in pts])
+    assert np.abs(g - want).max() <= 1e-4 * np.abs(got).max()
+    assert _walls_zero(got)
