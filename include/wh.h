@@ -80,7 +80,14 @@ typedef enum {
  * accumulator, the weights and everything in the outer solvers stay FP64. */
 typedef enum { WH_FP64 = 0, WH_FP32_STATE = 1 } wh_precision;
 
-typedef enum { WH_SOLVER_FPI = 0, WH_SOLVER_GMRES = 1 } wh_solver;
+/* Outer solvers of (I - S_h) v = b.  FPI: the fixed-point iteration of Alg. 1.
+ * GMRES: restarted GMRES(m) (Sec. 5.3).  CG: conjugate gradients in the inner
+ * product <u, v> = sum_i u_i v_i / c^2_i, in which c^2 Delta_h and therefore
+ * S_h are self-adjoint; the eigenvalues of A = I - S_h are 1 - beta_d in
+ * [0, 3/2] (the discrete filter function lies in [-1/2, 1], Sec. 4.2.1), so A
+ * is positive definite away from exact resonance.  CG uses three vectors of
+ * the Krylov workspace and needs a workspace sized for restart >= 2. */
+typedef enum { WH_SOLVER_FPI = 0, WH_SOLVER_GMRES = 1, WH_SOLVER_CG = 2 } wh_solver;
 
 /* Time parameters of one WaveHoltz application (explicit correction recipe,
  * Appendix A.1; stability limit of Sec. 3.2, eq. dtForCartesian):
@@ -111,7 +118,7 @@ typedef void (*wh_iter_callback)(int32_t k, double rel_res, void *user);
 typedef struct {
   int32_t method;   /* wh_solver */
   int32_t restart;  /* GMRES restart length m (1..WH_MAX_RESTART); ignored by FPI */
-  int32_t maxit;    /* maximum applies (FPI) or Arnoldi steps (GMRES) */
+  int32_t maxit;    /* maximum applies (FPI), Arnoldi steps (GMRES) or iterations (CG) */
   int32_t flags;    /* reserved, must be 0 */
   double rtol;      /* stop when ||b - A v||_2 <= rtol ||b||_2; 0 = run maxit (FPI) */
   wh_iter_callback on_iter; /* nullable */
@@ -119,8 +126,8 @@ typedef struct {
 } wh_solve_opts;
 
 /* Results of wh_solve.  For FPI the residual of iterate k is v^k - v^{k-1}
- * (= b - A v^{k-1}); for GMRES it is the true residual b - A v at exit.
- *   iters       FPI applies or GMRES Arnoldi steps performed
+ * (= b - A v^{k-1}); for GMRES and CG it is the true residual b - A v at exit.
+ *   iters       FPI applies, GMRES Arnoldi steps or CG iterations performed
  *   applies     WaveHoltz applications performed (includes b and restarts)
  *   rel_res     ||r||_2 / ||b||_2 at exit
  *   scaled_res  ||r||_2 / sqrt(number of nodes) (the paper's scaled norm, Sec. 7)
@@ -147,7 +154,7 @@ typedef struct {
   double point_steps;
 } wh_solve_info;
 
-#define WH_MAX_RESTART 256
+#define WH_MAX_RESTART 4096
 
 /* Version of the ABI (major * 10000 + minor * 100 + patch). */
 WH_API int32_t wh_version(void);
@@ -223,7 +230,7 @@ WH_API wh_status wh_apply(wh_ctx *ctx, const double *v, double *out, int32_t wit
  * (eq. MevalII).  Device pointers; Av may not alias v. */
 WH_API wh_status wh_apply_A(wh_ctx *ctx, const double *v, double *Av);
 
-/* Solve (I - S_h) v = b, b = W_h(0, f), by FPI (Alg. 1) or restarted GMRES.
+/* Solve (I - S_h) v = b, b = W_h(0, f), by FPI (Alg. 1), restarted GMRES or CG.
  * v (device) holds the initial guess on entry and the iterate on exit.
  * info (nullable) receives the statistics.  Returns WH_ENOTCONV if rtol > 0
  * was not reached within maxit (v still holds the last iterate),
@@ -239,14 +246,17 @@ WH_API wh_status wh_helmholtz_residual(wh_ctx *ctx, const double *u, double *res
  * library's deterministic reduction order.  Synchronises the stream. */
 WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *out);
 
-/* Tuning of the time-stepping kernels: kblock = leapfrog steps fused per
- * pass over the grid (1..8; 0 = automatic), tile_x/tile_y = owned tile
- * shape of a work-group in nodes (0 = automatic).  Results do not depend on
- * these values beyond floating-point reassociation-free identity: every
- * setting computes the same arithmetic per node and step. */
+/* Tuning of the time-stepping kernels.  kblock = leapfrog steps fused per
+ * pass over the grid: 0 = automatic, 1 = one kernel launch per step, 2..4 =
+ * temporally blocked passes (2-D grids; 3-D grids always take one step per
+ * launch).  tile_x, tile_y are reserved and must be 0 (the blocked kernel's
+ * tile is fixed by the precision, the order and kblock).  Every setting
+ * evaluates the same expression per node and step; results agree with each
+ * other to rounding. */
 WH_API wh_status wh_set_tuning(wh_ctx *ctx, int32_t kblock, int32_t tile_x, int32_t tile_y);
 
-/* Current tuning after automatic choices have been resolved for this grid. */
+/* Current tuning after automatic choices have been resolved for this grid:
+ * steps per pass and the owned tile of one work-group in nodes. */
 WH_API wh_status wh_get_tuning(const wh_ctx *ctx, int32_t *kblock, int32_t *tile_x, int32_t *tile_y);
 
 /* Timing of the time-stepping kernels, measured with HIP events recorded on

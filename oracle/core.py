@@ -376,5 +376,47 @@ def gmres(grid: Grid, c2, f, tp: dict, restart: int = 50, rtol: float = 1e-8, ma
     return x.reshape(grid.shape), dict(iters=total, rel_res=hist[-1], hist=hist, bnorm=bnorm)
 
 
+def cg(grid: Grid, c2, f, tp: dict, rtol: float = 1e-8, maxit: int = 1000, x0=None,
+       fixed_iters: int | None = None):
+    """Conjugate gradients on (I - S_h) v = b, b = W_h(0, f), in the inner
+    product <u, w> = sum_i u_i w_i / c^2_i.
+
+    S_h is a polynomial in c^2 Delta_h, which is self-adjoint in that inner
+    product, and its eigenvalues are beta_d in [-1/2, 1] (Sec. 4.2.1 and
+    Sec. 5.3), so I - S_h is positive semi-definite there.  Textbook
+    Hestenes-Stiefel recurrences; stops when the recursively updated residual
+    satisfies ||r||_2 <= rtol ||b||_2, or after exactly fixed_iters iterations.
+    Returns (x, info) with info = dict(iters, rel_res (true residual), hist).
+    """
+    mask = interior_mask(grid)
+    wgt = 1.0 / (np.full(grid.shape, float(c2)) if np.isscalar(c2) else np.asarray(c2, dtype=np.float64))
+    ip = lambda a, b: float(np.sum(a * b * wgt))
+    A = lambda vec: apply_A(grid, c2, vec, tp)
+    b = apply(grid, c2, f, np.zeros(grid.shape), tp, with_forcing=True)
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros(grid.shape) if x0 is None else _prep(grid, x0, "x0").copy()
+    x[~mask] = 0.0
+    r = b - A(x)
+    p = r.copy()
+    rr = ip(r, r)
+    hist = [float(np.linalg.norm(r)) / bnorm]
+    limit = fixed_iters if fixed_iters is not None else maxit
+    k = 0
+    while k < limit:
+        if fixed_iters is None and hist[-1] <= rtol:
+            break
+        q = A(p)
+        alpha = rr / ip(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = ip(r, r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+    true_rel = float(np.linalg.norm(b - A(x))) / bnorm
+    return x, dict(iters=k, rel_res=true_rel, hist=hist, bnorm=bnorm)
+
+
 def max_threads() -> int:
     return int(_load().orc_max_threads())

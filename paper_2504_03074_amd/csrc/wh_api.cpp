@@ -272,6 +272,14 @@ wh_status drain_profile(wh_ctx *c) {
   return WH_OK;
 }
 
+// Leapfrog steps fused per pass for the current grid (1 = the per-step kernel).
+int steps_per_pass(const wh_ctx *c) {
+  if (c->dim != 2) return 1;
+  if (c->kblock == 1) return 1;
+  if (c->kblock >= 2) return c->kblock;
+  return 4;  // automatic choice for 2-D grids
+}
+
 // One WaveHoltz application.  mode: ACCUMULATE (acc keeps the filter),
 // FINAL_FILTER (out = filtered) or FINAL_A (out = v - filtered).
 wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double *out, double *w_final) {
@@ -289,23 +297,53 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
     WH_TRY(take_events(c, &ev0, &ev1));
     WH_HIP(c, hipEventRecord(ev0, c->stream));
   }
-  void *prev = c->W[0], *cur = c->W[1];
-  for (int64_t n = 1; n < N; ++n) {
-    const int m = (n == N - 1) ? mode : wh::ACCUMULATE;
-    WH_HIP(c, wh::launch_step(fp32, g, cur, prev, c->acc, c2, f, forcing ? c->frc[(size_t)n] : 0.0,
-                              c->wts[(size_t)n + 1], m, v, out, c->stream));
-    std::swap(prev, cur);
+  const int K = steps_per_pass(c);
+  const double T = (double)state_bytes(c);
+  const double aux = (c2 ? T : 0.0) + (f ? T : 0.0);  // c^2 and f reads per node and launch
+  int64_t launches = 0;
+  double bytes_per_node = 0.0;
+  void *cur;
+  if (K == 1) {
+    void *prev = c->W[0];
+    cur = c->W[1];
+    for (int64_t n = 1; n < N; ++n) {
+      const int m = (n == N - 1) ? mode : wh::ACCUMULATE;
+      WH_HIP(c, wh::launch_step(fp32, g, cur, prev, c->acc, c2, f, forcing ? c->frc[(size_t)n] : 0.0,
+                                c->wts[(size_t)n + 1], m, v, out, c->stream));
+      std::swap(prev, cur);
+      ++launches;
+      // W^n, W^{n-1} read, W^{n+1} written, accumulator read and written
+      bytes_per_node += 3.0 * T + aux + 16.0;
+    }
+  } else {
+    void *ip = c->W[0], *ic = c->W[1], *op = c->W[2], *oc = c->W[3];
+    const int64_t total = N - 1;  // steps after the first
+    int64_t done = 0;
+    while (done < total) {
+      const int ks = (int)std::min<int64_t>(K, total - done);
+      wh::BlockCoef coef{};
+      for (int s = 0; s < ks; ++s) {
+        const int64_t n = 1 + done + s;  // step from level n to n + 1
+        coef.gn[s] = forcing ? c->frc[(size_t)n] : 0.0;
+        coef.wn[s] = c->wts[(size_t)n + 1];
+      }
+      const int m = (done + ks == total) ? mode : wh::ACCUMULATE;
+      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
+                                          c->stream));
+      std::swap(ip, op);
+      std::swap(ic, oc);
+      done += ks;
+      ++launches;
+      // two levels read and two written, accumulator read and written
+      bytes_per_node += 4.0 * T + aux + 16.0;
+    }
+    cur = ic;
   }
   if (c->profiling) {
     WH_HIP(c, hipEventRecord(ev1, c->stream));
     const double interior = interior_nodes(c);
-    const double T = (double)state_bytes(c);
-    // per launch and interior node: W^n, W^{n-1} read, W^{n+1} written, c^2 and
-    // f read when present, FP64 accumulator read and written
-    const double per = 3.0 * T + (c2 ? T : 0.0) + (f ? T : 0.0) + 16.0;
     const double extra = (mode == wh::FINAL_A) ? 8.0 : 0.0;  // v read on the last launch
-    c->pending.push_back({ev0, ev1, N - 1, interior * (per * (double)(N - 1) + extra),
-                          interior * (double)(N - 1)});
+    c->pending.push_back({ev0, ev1, launches, interior * (bytes_per_node + extra), interior * (double)(N - 1)});
     if (c->pending.size() >= 256) WH_TRY(drain_profile(c));
   }
   if (w_final) WH_HIP(c, wh::launch_from_state(fp32, cur, w_final, c->nodes, c->stream));
@@ -594,6 +632,9 @@ wh_status wh_set_c2(wh_ctx *c, const double *c2, int32_t on_device) {
   } else {
     WH_HIP(c, hipMemcpyAsync(c->c2, src, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
   }
+  // wall values are ignored by contract; the blocked kernels evaluate wall
+  // nodes (where the Laplacian is exactly 0), so give them a finite value
+  WH_HIP(c, wh::launch_set_walls(c->prec == WH_FP32_STATE, geometry(c, 1.0), c->c2, 1.0, c->stream));
   WH_HIP(c, hipStreamSynchronize(c->stream));
   c->c2_is_const = false;
   c->c2_value = 1.0;
@@ -607,6 +648,8 @@ wh_status wh_set_source(wh_ctx *c, const double *f, int32_t on_device) {
   WH_TRY(set_device(c));
   if (on_device) WH_TRY(check_dev(c, f, "f"));
   WH_TRY(upload_field(c, f, on_device, c->f));
+  // wall values are ignored by contract: the source is 0 there
+  WH_HIP(c, wh::launch_set_walls(c->prec == WH_FP32_STATE, geometry(c, 1.0), c->f, 0.0, c->stream));
   c->f_set = true;
   return WH_OK;
 }
@@ -698,8 +741,9 @@ wh_status wh_helmholtz_residual(wh_ctx *c, const double *u, double *res, double 
 
 wh_status wh_set_tuning(wh_ctx *c, int32_t kblock, int32_t tile_x, int32_t tile_y) {
   WH_TRY(need(c, true, false, false, false, false));
-  if (kblock < 0 || kblock > 8) return fail(c, WH_EINVAL, "kblock must be in 0..8");
-  if (tile_x < 0 || tile_y < 0 || tile_x > 1024 || tile_y > 1024) return fail(c, WH_EINVAL, "bad tile shape");
+  if (kblock < 0 || kblock > wh::kMaxBlockSteps)
+    return fail(c, WH_EINVAL, "kblock must be in 0..%d", wh::kMaxBlockSteps);
+  if (tile_x != 0 || tile_y != 0) return fail(c, WH_EINVAL, "tile_x and tile_y are reserved and must be 0");
   c->kblock = kblock;
   c->tile_x = tile_x;
   c->tile_y = tile_y;
@@ -709,9 +753,14 @@ wh_status wh_set_tuning(wh_ctx *c, int32_t kblock, int32_t tile_x, int32_t tile_
 wh_status wh_get_tuning(const wh_ctx *c, int32_t *kblock, int32_t *tile_x, int32_t *tile_y) {
   if (!c || !kblock || !tile_x || !tile_y) return WH_EINVAL;
   if (!c->grid_set) return WH_ESTATE;
-  *kblock = c->kblock > 0 ? c->kblock : 1;
-  *tile_x = c->tile_x;
-  *tile_y = c->tile_y;
+  const int K = steps_per_pass(c);
+  *kblock = K;
+  if (K >= 2) {
+    wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, K, tile_x, tile_y);
+  } else {
+    *tile_x = 64;
+    *tile_y = 4;
+  }
   return WH_OK;
 }
 
@@ -897,20 +946,116 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
   return st;
 }
 
+// Conjugate gradients on A v = b in the inner product <u, w> = sum u w / c^2.
+// Iteration k keeps <r, r>_w and ||r||^2 in device slot (k & 1); the update
+// kernels read their coefficients from device memory, so each iteration
+// synchronises with the host once (for the convergence test).
+static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info) {
+  if (c->ws_restart < 2) return fail(c, WH_ENOMEM, "CG needs a workspace sized for restart >= 2");
+  const int64_t N = c->nodes;
+  const int nb = wh::reduction_blocks(N);
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  const void *c2w = c->c2_is_const ? nullptr : c->c2;
+  double *r = c->V, *p = c->V + c->ldv, *q = c->V + 2 * c->ldv;
+  const int S_PQ = 2;
+  auto slot = [](int64_t k) { return 4 + 2 * (int)(k & 1); };  // [<r,r>_w, <r,r>]
+
+  int applies = 0;
+  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, N, c->stream));
+  WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));  // b = W_h(0, f)
+  ++applies;
+  double bb;
+  WH_TRY(dot_dev(c, c->b, c->b, 0));
+  WH_TRY(fetch_scalars(c, 0, 1, &bb));
+  const double bnorm = std::sqrt(bb);
+  if (!std::isfinite(bnorm)) return fail(c, WH_ENONFINITE, "||b|| is not finite");
+
+  // r = b - A x, p = r, slot(k) = [<r,r>_w, <r,r>]
+  auto restart = [&](int64_t k, double *rel) -> wh_status {
+    WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
+    ++applies;
+    WH_HIP(c, wh::launch_sub(c->b, c->tmp, r, N, c->stream));
+    WH_HIP(c, wh::launch_wdot(r, r, c2w, fp32, N, c->partials, nb, c->stream));
+    WH_TRY(reduce_to(c, 1, slot(k)));
+    WH_TRY(dot_dev(c, r, r, slot(k) + 1));
+    WH_HIP(c, hipMemcpyAsync(p, r, (size_t)N * 8, hipMemcpyDeviceToDevice, c->stream));
+    double ee;
+    WH_TRY(fetch_scalars(c, slot(k) + 1, 1, &ee));
+    *rel = bnorm > 0.0 ? std::sqrt(ee) / bnorm : 0.0;
+    return WH_OK;
+  };
+
+  double rel = 0.0, rel0 = -1.0;
+  int64_t k = 0;
+  wh_status st = WH_OK;
+  WH_TRY(restart(k, &rel));
+  rel0 = rel;
+  while (bnorm > 0.0 && rel > o->rtol && k < o->maxit) {
+    WH_TRY(apply_impl(c, p, false, wh::FINAL_A, q, nullptr));  // q = A p
+    ++applies;
+    WH_HIP(c, wh::launch_wdot(p, q, c2w, fp32, N, c->partials, nb, c->stream));
+    WH_TRY(reduce_to(c, 1, S_PQ));
+    const int cur = slot(k), nxt = slot(k + 1);
+    WH_HIP(c, wh::launch_cg_update(x, r, p, q, c2w, fp32, c->scal + cur, c->scal + S_PQ, N, c->partials, nb,
+                                   c->stream));
+    WH_TRY(reduce_to(c, 2, nxt));
+    ++k;
+    double sc[8];
+    WH_TRY(fetch_scalars(c, 0, 8, sc));
+    const double pq = sc[S_PQ];
+    const double ee = sc[nxt + 1];
+    if (!std::isfinite(pq) || !std::isfinite(ee)) {
+      st = fail(c, WH_ENONFINITE, "CG became non-finite at iteration %lld", (long long)k);
+      break;
+    }
+    if (!(pq > 0.0)) {
+      st = fail(c, WH_ENOTCONV, "CG breakdown: <p, A p> = %g <= 0 at iteration %lld", pq, (long long)k);
+      break;
+    }
+    rel = bnorm > 0.0 ? std::sqrt(ee) / bnorm : 0.0;
+    if (o->on_iter) o->on_iter((int32_t)k, rel, o->user);
+    if (rel <= o->rtol) {
+      // confirm with the true residual; continue from it if rounding drifted
+      WH_TRY(restart(k, &rel));
+      if (rel <= o->rtol) break;
+      continue;
+    }
+    WH_HIP(c, wh::launch_xpay(r, p, c->scal + nxt, c->scal + cur, N, c->stream));
+  }
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->iters = (int32_t)k;
+    info->applies = applies;
+    info->bnorm = bnorm;
+    info->rel_res = rel;
+    info->scaled_res = rel * bnorm / std::sqrt((double)N);
+    info->cr_last = (k > 0 && rel0 > 0.0) ? std::pow(rel / rel0, 1.0 / (double)k) : NAN;
+    info->cr_avg = info->cr_last;
+    info->ecr = std::pow(info->cr_avg, 1.0 / c->tp.periods);
+    info->point_steps = applies * point_steps_per_apply(c);
+  }
+  if (st == WH_OK && rel > o->rtol)
+    st = fail(c, WH_ENOTCONV, "CG reached maxit = %d at relative residual %g", o->maxit, rel);
+  return st;
+}
+
 wh_status wh_solve(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
   WH_TRY(need(c, true, true, true, true, true));
   if (!o) return fail(c, WH_EINVAL, "opts is NULL");
   if (o->flags != 0) return fail(c, WH_EINVAL, "opts.flags must be 0");
   if (o->maxit < 1) return fail(c, WH_EINVAL, "maxit must be >= 1");
   if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(c, WH_EINVAL, "rtol must be finite and >= 0");
-  if (o->method != WH_SOLVER_FPI && o->method != WH_SOLVER_GMRES) return fail(c, WH_EINVAL, "unknown method");
+  if (o->method != WH_SOLVER_FPI && o->method != WH_SOLVER_GMRES && o->method != WH_SOLVER_CG)
+    return fail(c, WH_EINVAL, "unknown method");
   WH_TRY(set_device(c));
   WH_TRY(check_dev(c, v, "v"));
   if (info) std::memset(info, 0, sizeof *info);
   const auto t0 = std::chrono::steady_clock::now();
   wh_status st;
   try {
-    st = o->method == WH_SOLVER_FPI ? solve_fpi(c, o, v, info) : solve_gmres(c, o, v, info);
+    if (o->method == WH_SOLVER_FPI) st = solve_fpi(c, o, v, info);
+    else if (o->method == WH_SOLVER_GMRES) st = solve_gmres(c, o, v, info);
+    else st = solve_cg(c, o, v, info);
   } catch (const std::bad_alloc &) {
     st = fail(c, WH_ENOMEM, "host allocation failed");
   } catch (...) {

@@ -1,0 +1,276 @@
+// Temporally blocked leapfrog + filter kernel for 2-D grids (gfx950).
+//
+// One work-group advances a tile of the grid by K leapfrog steps per pass
+// over HBM, instead of one:  W^{n-1}, W^n, c^2 (and f) are read once, K steps
+// of the explicit scheme (Sec. 4.2.1, eq. WaveSchemeexplicit) are taken on
+// chip, the filter terms w_{n+s} W^{n+s} (eq. updateDiscreteExplicit) are
+// added to the FP64 accumulator in registers, and W^{n+K-1}, W^{n+K} and the
+// accumulator are written once.
+//
+// Layout on chip.  A work-group is NW wavefronts of 64 lanes.  Lane l of
+// every wave holds grid column x0 - H + l; wave w holds rows
+// y0 - H + w*RS .. + RS - 1 of that column in registers (W^n, W^{n-1}, c^2,
+// f, accumulator).  Neighbours along x come from the adjacent lanes through
+// DPP wave shifts (no LDS traffic); neighbours along y are in the lane's own
+// registers except across a wave boundary, where the r = p/2 edge rows are
+// exchanged through a small double-buffered LDS array (one barrier per step).
+// Values at the edges of the region are wrong after each step; the error
+// front moves r nodes per step, so with halo H = K*r the owned tile
+// (64 - 2H) x (NW*RS - 2H) is exact after K steps.
+//
+// Walls.  Nodes beyond a wall are loaded as the odd reflection of interior
+// nodes (c^2 as the even reflection).  The update is evaluated as the same
+// expression on symmetric neighbour-pair sums at every node, so mirrored
+// nodes stay exact negatives of their originals and wall nodes stay exactly
+// zero through all K steps; no per-step boundary fix-up is needed.  Wall
+// nodes are written as 0 explicitly.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wh_internal.h"
+
+namespace wh {
+namespace {
+
+// lane l receives the value of lane l-1 (x - 1); lane 0 receives 0
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+// lane l receives the value of lane l+1 (x + 1); lane 63 receives 0
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Odd periodic extension of a node index i of an axis with n cells:
+// returns the interior/wall index and the sign of the reflection.
+__device__ __forceinline__ int reflect(int i, int n, float &sign) {
+  const int two_n = 2 * n;
+  int m = i % two_n;
+  if (m < 0) m += two_n;
+  if (m <= n) return m;
+  sign = -sign;
+  return two_n - m;
+}
+
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
+__global__ __launch_bounds__(64 * NW) void block_steps_kernel(
+    StepGeom g, int ksteps, int tiles_x, int tiles_total, const T *__restrict__ in_prev,
+    const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
+    const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
+    double *__restrict__ out) {
+  constexpr int R = P / 2;
+  constexpr int H = K * R;
+  constexpr int OX = 64 - 2 * H;
+  constexpr int OY = NW * RS - 2 * H;
+  static_assert(OX > 0 && OY > 0, "tile too small for the halo");
+  static_assert(RS >= R, "each wave must hold at least r rows");
+
+  // XCD-aware tile order: consecutive work-groups are dispatched round-robin
+  // over the 8 XCDs; give each XCD a contiguous run of tiles so that the halo
+  // re-reads of neighbouring tiles hit the same L2.
+  const int nblk = gridDim.x;
+  const int b = blockIdx.x;
+  const int per_xcd = (nblk + 7) / 8;
+  const int tile = (b % 8) * per_xcd + (b / 8);
+  if (tile >= tiles_total) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int x0 = tx * OX, y0 = ty * OY;
+  const int gx = x0 - H + lane;
+  const int gy0 = y0 - H + wave * RS;
+
+  __shared__ T halo[2][NW][2][R][64];
+
+  T A[RS], B[RS], C2[RS], F[RS];
+  double ACC[RS];
+  uint32_t own = 0;  // bit q: row q of this lane is an owned interior node
+
+  float sx = 1.0f;
+  const int ix = reflect(gx, g.nx, sx);
+  const bool col_owned = lane >= H && lane < H + OX && gx <= g.nx;
+  const bool col_wall = ix == 0 || ix == g.nx;
+#pragma unroll
+  for (int q = 0; q < RS; ++q) {
+    float s = sx;
+    const int gy = gy0 + q;
+    const int iy = reflect(gy, g.ny, s);
+    const int64_t id = (int64_t)ix + (int64_t)iy * g.sy;
+    const T sg = static_cast<T>(s);
+    B[q] = sg * in_prev[id];
+    A[q] = sg * in_cur[id];
+    C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
+    F[q] = FORCE ? sg * fg[id] : T(0);
+    const int r = wave * RS + q;
+    const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
+    const bool wall = col_wall || iy == 0 || iy == g.ny;
+    ACC[q] = 0.0;
+    if (in_tile && !wall) {
+      own |= 1u << q;
+      ACC[q] = acc[id];
+    } else if (in_tile) {
+      // wall node owned by this tile: its outputs are exactly 0
+      out_prev[id] = T(0);
+      out_cur[id] = T(0);
+      if (mode != ACCUMULATE) out[id] = 0.0;
+    }
+  }
+
+  const T kx = static_cast<T>(g.kx), ky = static_cast<T>(g.ky), kc = static_cast<T>(g.kc);
+
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    if (s < ksteps) {
+      T *cur = (s & 1) ? B : A;
+      T *prv = (s & 1) ? A : B;
+      // y-halo: publish this wave's edge rows, fetch the neighbours'
+      const int hb = s & 1;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        halo[hb][wave][0][k][lane] = cur[k];           // top rows
+        halo[hb][wave][1][k][lane] = cur[RS - R + k];  // bottom rows
+      }
+      __syncthreads();
+      T up[R], dn[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        up[k] = wave > 0 ? halo[hb][wave - 1][1][k][lane] : T(0);      // rows above: q = k - R
+        dn[k] = wave < NW - 1 ? halo[hb][wave + 1][0][k][lane] : T(0);  // rows below: q = RS + k
+      }
+      const T gn = static_cast<T>(coef.gn[s]);
+      const double wn = coef.wn[s];
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        auto row = [&](int qq) -> T {
+          if (qq < 0) return up[qq + R];
+          if (qq >= RS) return dn[qq - RS];
+          return cur[qq];
+        };
+        const T c = cur[q];
+        const T xl1 = from_left(c), xr1 = from_right(c);
+        T lap;
+        if (P == 2) {
+          lap = kx * (xl1 + xr1) + ky * (row(q - 1) + row(q + 1)) - kc * c;
+        } else {
+          const T xl2 = from_left(xl1), xr2 = from_right(xr1);
+          lap = kx * (T(16) * (xl1 + xr1) - (xl2 + xr2)) +
+                ky * (T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2))) - kc * c;
+        }
+        T nxt = T(2) * c - prv[q] + C2[q] * lap;
+        if (FORCE) nxt += gn * F[q];
+        prv[q] = nxt;
+        ACC[q] += wn * static_cast<double>(nxt);
+      }
+    }
+  }
+
+  // after ksteps steps the newest level is in B if ksteps is odd, else in A
+  const bool odd = ksteps & 1;
+#pragma unroll
+  for (int q = 0; q < RS; ++q) {
+    if (!((own >> q) & 1u)) continue;
+    const int64_t id = (int64_t)gx + (int64_t)(gy0 + q) * g.sy;  // owned nodes need no reflection
+    out_cur[id] = odd ? B[q] : A[q];
+    out_prev[id] = odd ? A[q] : B[q];
+    if (mode == ACCUMULATE) acc[id] = ACC[q];
+    else if (mode == FINAL_FILTER) out[id] = ACC[q];
+    else out[id] = v[id] - ACC[q];
+  }
+}
+
+template <typename T, int P, int K, int RS, int NW>
+hipError_t launch_typed(const StepGeom &g, int ksteps, const void *in_prev, const void *in_cur, void *out_prev,
+                        void *out_cur, double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
+                        const double *v, double *out, hipStream_t s) {
+  constexpr int H = K * (P / 2);
+  constexpr int OX = 64 - 2 * H;
+  constexpr int OY = NW * RS - 2 * H;
+  const int tiles_x = (g.nx + 1 + OX - 1) / OX;
+  const int tiles_y = (g.ny + 1 + OY - 1) / OY;
+  const int tiles = tiles_x * tiles_y;
+  const int blocks = ((tiles + 7) / 8) * 8;
+  const T *ip = static_cast<const T *>(in_prev);
+  const T *ic = static_cast<const T *>(in_cur);
+  T *op = static_cast<T *>(out_prev);
+  T *oc = static_cast<T *>(out_cur);
+  const T *cc = static_cast<const T *>(c2);
+  const T *ff = static_cast<const T *>(f);
+  dim3 grid(blocks), block(64 * NW);
+  if (f && c2)
+    block_steps_kernel<T, P, K, RS, NW, true, true><<<grid, block, 0, s>>>(g, ksteps, tiles_x, tiles, ip, ic, op, oc,
+                                                                          acc, cc, ff, coef, mode, v, out);
+  else if (f)
+    block_steps_kernel<T, P, K, RS, NW, true, false><<<grid, block, 0, s>>>(g, ksteps, tiles_x, tiles, ip, ic, op, oc,
+                                                                           acc, cc, ff, coef, mode, v, out);
+  else if (c2)
+    block_steps_kernel<T, P, K, RS, NW, false, true><<<grid, block, 0, s>>>(g, ksteps, tiles_x, tiles, ip, ic, op,
+                                                                           oc, acc, cc, ff, coef, mode, v, out);
+  else
+    block_steps_kernel<T, P, K, RS, NW, false, false><<<grid, block, 0, s>>>(g, ksteps, tiles_x, tiles, ip, ic, op,
+                                                                            oc, acc, cc, ff, coef, mode, v, out);
+  return hipGetLastError();
+}
+
+// Rows per lane and waves per work-group.  FP64 keeps 8 rows per lane (the
+// register arrays stay in VGPRs) in 16 waves; FP32 keeps 24 rows in 8 waves.
+template <typename T>
+struct BlockShape;
+template <>
+struct BlockShape<double> {
+  static constexpr int RS = 8, NW = 16;
+};
+template <>
+struct BlockShape<float> {
+  static constexpr int RS = 24, NW = 8;
+};
+
+template <typename T, int P>
+hipError_t dispatch_k(const StepGeom &g, int K, int ksteps, const void *ip, const void *ic, void *op, void *oc,
+                      double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode, const double *v,
+                      double *out, hipStream_t s) {
+  constexpr int RS = BlockShape<T>::RS, NW = BlockShape<T>::NW;
+  switch (K) {
+    case 2: return launch_typed<T, P, 2, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 3: return launch_typed<T, P, 3, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 4: return launch_typed<T, P, 4, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool block_config_supported(int order, int K) { return (order == 2 || order == 4) && K >= 2 && K <= kMaxBlockSteps; }
+
+void block_tile_shape(bool fp32, int order, int K, int *owned_x, int *owned_y) {
+  const int H = K * (order / 2);
+  *owned_x = 64 - 2 * H;
+  *owned_y = fp32 ? BlockShape<float>::RS * BlockShape<float>::NW - 2 * H
+                  : BlockShape<double>::RS * BlockShape<double>::NW - 2 * H;
+}
+
+hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int ksteps, const void *in_prev,
+                                 const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
+                                 const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
+                                 hipStream_t s) {
+  if (ksteps < 1 || ksteps > K || !block_config_supported(g.order, K)) return hipErrorInvalidValue;
+  if (fp32) {
+    if (g.order == 2) return dispatch_k<float, 2>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+    return dispatch_k<float, 4>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+  }
+  if (g.order == 2) return dispatch_k<double, 2>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+  return dispatch_k<double, 4>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+}
+
+}  // namespace wh

@@ -39,19 +39,23 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
                        const void *c2, const void *f, double gn, double wn, int mode,
                        const double *v, double *out, hipStream_t s);
 
-// Temporally blocked step: K leapfrog steps per pass over the grid for a
-// 2-D grid.  in_prev/in_cur hold W^{n-1}, W^n; out_prev/out_cur receive
-// W^{n+K-1}, W^{n+K}.  gn[j], wn[j] for j = 0..K-1 belong to the steps
-// producing W^{n+1+j}.  The last pass of an application uses mode != 0.
+// Temporally blocked steps for 2-D grids: ksteps <= K leapfrog steps per pass
+// over the grid (K fixes the halo K*p/2 and the tile shape).  in_prev/in_cur
+// hold W^{n-1}, W^n; out_prev/out_cur receive W^{n+ks-1}, W^{n+ks}.  gn[s],
+// wn[s] belong to the step producing W^{n+1+s}.  The last pass of an
+// application uses mode != ACCUMULATE.
+constexpr int kMaxBlockSteps = 4;
 struct BlockCoef {
-  double gn[8];
-  double wn[8];
+  double gn[kMaxBlockSteps];
+  double wn[kMaxBlockSteps];
 };
-hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int tile_x, int tile_y,
-                                 const void *in_prev, const void *in_cur, void *out_prev, void *out_cur,
-                                 double *acc, const void *c2, const void *f, const BlockCoef &coef,
-                                 int mode, const double *v, double *out, hipStream_t s);
-bool block_config_supported(bool fp32, int order, int K, int tile_x, int tile_y);
+hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int ksteps, const void *in_prev,
+                                 const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
+                                 const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
+                                 hipStream_t s);
+bool block_config_supported(int order, int K);
+// Owned tile (nodes) of one work-group of the blocked kernel.
+void block_tile_shape(bool fp32, int order, int K, int *owned_x, int *owned_y);
 
 // Convert/copy helpers.
 hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s);
@@ -64,6 +68,16 @@ hipError_t launch_mdot(const double *V, int64_t ldv, int k, const double *w, int
                        int nb, hipStream_t s);
 // out[i] = sum_b partials[i * nb + b] (block-tree order).
 hipError_t launch_reduce_rows(const double *partials, int nb, int k, double *out, hipStream_t s);
+// partials of sum_e x_e y_e / c2_e (c2 null: plain dot), one row of nb
+hipError_t launch_wdot(const double *x, const double *y, const void *c2, bool fp32_c2, int64_t n, double *partials,
+                       int nb, hipStream_t s);
+// CG step: a = *num / *den; x += a p; r -= a q; partials of <r,r>_{1/c2}
+// (row 0) and <r,r> (row 1).  c2 null: unweighted.
+hipError_t launch_cg_update(double *x, double *r, const double *p, const double *q, const void *c2, bool fp32_c2,
+                            const double *num, const double *den, int64_t n, double *partials, int nb,
+                            hipStream_t s);
+// p = r + (*num / *den) p
+hipError_t launch_xpay(const double *r, double *p, const double *num, const double *den, int64_t n, hipStream_t s);
 // w[e] -= sum_i coef[i] * V_i[e]  (coef on device)
 hipError_t launch_block_axpy(const double *V, int64_t ldv, int k, const double *coef, double *w, int64_t n,
                              hipStream_t s);
@@ -85,5 +99,7 @@ hipError_t launch_interior_stats(const StepGeom &g, const double *src, double *p
 hipError_t launch_helmholtz_residual(const StepGeom &g_unscaled, const double *u, const void *c2, bool fp32_c2,
                                      const void *f, bool fp32_f, double omega2, double *res, hipStream_t s);
 hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t s);
+// Overwrite the wall nodes of a state-precision node array with `value`.
+hipError_t launch_set_walls(bool fp32, const StepGeom &g, void *a, double value, hipStream_t s);
 
 }  // namespace wh

@@ -185,6 +185,17 @@ __global__ void from_state_kernel(const T *__restrict__ src, double *__restrict_
     dst[e] = static_cast<double>(src[e]);
 }
 
+// Overwrite the wall nodes of a node array with `value`.
+template <typename T>
+__global__ void set_walls_kernel(StepGeom g, T *__restrict__ a, T value) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < g.nodes; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % g.sy;
+    const int64_t j = (e / g.sy) % (g.ny + 1);
+    const int64_t k = (g.dim == 3) ? e / g.sz : 0;
+    if (i == 0 || i == g.nx || j == 0 || j == g.ny || (g.dim == 3 && (k == 0 || k == g.nz))) a[e] = value;
+  }
+}
+
 __global__ void fill_kernel(double *__restrict__ dst, double value, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = value;
@@ -221,6 +232,53 @@ __global__ __launch_bounds__(kRedThreads) void mdot_kernel(const double *__restr
     s += x[e] * w[e];
   s = block_sum(s, sm);
   if (threadIdx.x == 0) partials[(int64_t)vec * nb + blockIdx.x] = s;
+}
+
+// partials of sum_e x_e y_e / c2_e (the inner product in which c^2 Delta_h,
+// and hence the WaveHoltz operator, is self-adjoint)
+template <typename TC>
+__global__ __launch_bounds__(kRedThreads) void wdot_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                                                           const TC *__restrict__ c2, int64_t n,
+                                                           double *__restrict__ partials, int nb) {
+  __shared__ double sm[4];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += (int64_t)nb * kRedThreads)
+    s += x[e] * y[e] / static_cast<double>(c2[e]);
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x += a p, r -= a q with a = num/den read from device memory; partials of
+// <r, r>_w (row 0) and <r, r> (row 1) of the updated residual.
+template <typename TC>
+__global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double *__restrict__ x, double *__restrict__ r,
+                                                                const double *__restrict__ p,
+                                                                const double *__restrict__ q,
+                                                                const TC *__restrict__ c2, const double *__restrict__ num,
+                                                                const double *__restrict__ den, int64_t n,
+                                                                double *__restrict__ partials, int nb) {
+  __shared__ double sm[4];
+  const double a = *num / *den;
+  double sw = 0.0, se = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += (int64_t)nb * kRedThreads) {
+    x[e] += a * p[e];
+    const double re = r[e] - a * q[e];
+    r[e] = re;
+    se += re * re;
+    sw += re * re / (c2 ? static_cast<double>(c2[e]) : 1.0);
+  }
+  sw = block_sum(sw, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sw;
+  se = block_sum(se, sm);
+  if (threadIdx.x == 0) partials[nb + blockIdx.x] = se;
+}
+
+// p = r + (num/den) p
+__global__ void xpay_kernel(const double *__restrict__ r, double *__restrict__ p, const double *__restrict__ num,
+                            const double *__restrict__ den, int64_t n) {
+  const double b = *num / *den;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = r[e] + b * p[e];
 }
 
 __global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double *__restrict__ partials, int nb,
@@ -401,6 +459,12 @@ hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n,
   return hipGetLastError();
 }
 
+hipError_t launch_set_walls(bool fp32, const StepGeom &g, void *a, double value, hipStream_t s) {
+  if (fp32) set_walls_kernel<float><<<flat_blocks(g.nodes), 256, 0, s>>>(g, static_cast<float *>(a), (float)value);
+  else set_walls_kernel<double><<<flat_blocks(g.nodes), 256, 0, s>>>(g, static_cast<double *>(a), value);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t s) {
   fill_kernel<<<flat_blocks(n), 256, 0, s>>>(dst, value, n);
   return hipGetLastError();
@@ -421,6 +485,35 @@ hipError_t launch_mdot(const double *V, int64_t ldv, int k, const double *w, int
 
 hipError_t launch_reduce_rows(const double *partials, int nb, int k, double *out, hipStream_t s) {
   reduce_rows_kernel<<<(unsigned)k, kRedThreads, 0, s>>>(partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_wdot(const double *x, const double *y, const void *c2, bool fp32_c2, int64_t n, double *partials,
+                       int nb, hipStream_t s) {
+  if (!c2) {
+    mdot_kernel<<<dim3((unsigned)nb, 1u), kRedThreads, 0, s>>>(x, 0, y, n, partials, nb);
+  } else if (fp32_c2) {
+    wdot_kernel<float><<<(unsigned)nb, kRedThreads, 0, s>>>(x, y, static_cast<const float *>(c2), n, partials, nb);
+  } else {
+    wdot_kernel<double><<<(unsigned)nb, kRedThreads, 0, s>>>(x, y, static_cast<const double *>(c2), n, partials, nb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double *x, double *r, const double *p, const double *q, const void *c2, bool fp32_c2,
+                            const double *num, const double *den, int64_t n, double *partials, int nb,
+                            hipStream_t s) {
+  if (fp32_c2)
+    cg_update_kernel<float><<<(unsigned)nb, kRedThreads, 0, s>>>(x, r, p, q, static_cast<const float *>(c2), num, den,
+                                                                n, partials, nb);
+  else
+    cg_update_kernel<double><<<(unsigned)nb, kRedThreads, 0, s>>>(x, r, p, q, static_cast<const double *>(c2), num,
+                                                                 den, n, partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpay(const double *r, double *p, const double *num, const double *den, int64_t n, hipStream_t s) {
+  xpay_kernel<<<flat_blocks(n), 256, 0, s>>>(r, p, num, den, n);
   return hipGetLastError();
 }
 

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libwh.so")
 WH_OK, WH_EINVAL, WH_ENOMEM, WH_EDEVICE, WH_EUNSTABLE, WH_ENOTCONV, WH_ENONFINITE, WH_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 WH_FP64, WH_FP32_STATE = 0, 1
-WH_SOLVER_FPI, WH_SOLVER_GMRES = 0, 1
-WH_MAX_RESTART = 256
+WH_SOLVER_FPI, WH_SOLVER_GMRES, WH_SOLVER_CG = 0, 1, 2
+WH_MAX_RESTART = 4096
 
 
 class WhError(RuntimeError):
@@ -373,7 +373,7 @@ class Solver:
     def solve(self, method="gmres", rtol=1e-8, maxit=1000, restart=None, v0=None, callback=None):
         v = self.new() if v0 is None else v0.clone()
         opts = wh_solve_opts()
-        opts.method = WH_SOLVER_GMRES if method == "gmres" else WH_SOLVER_FPI
+        opts.method = {"gmres": WH_SOLVER_GMRES, "fpi": WH_SOLVER_FPI, "cg": WH_SOLVER_CG}[method]
         opts.restart = int(self.restart if restart is None else restart)
         opts.maxit = int(maxit)
         opts.flags = 0

@@ -290,6 +290,38 @@ def test_gmres_converges_to_direct_solve(order, dim, n):
     assert np.linalg.norm(res) / np.linalg.norm(f) < 1e-10
 
 
+@pytest.mark.parametrize("order", [2, 4])
+def test_cg_converges_to_direct_solve(order):
+    """CG in the 1/c^2-weighted inner product reaches the discrete Helmholtz
+    solution (variable c^2, non-square grid)."""
+    grid = oc.Grid(2, (20, 15), order)
+    g = wl.random_field(grid.shape, seed=23, zero_walls=False)
+    c2 = 0.5 + 1.5 / (1 + np.exp(-g))
+    x = oc.coords(grid)
+    f = np.exp(-50 * ((x[0] - 0.3) ** 2 + (x[1] - 0.6) ** 2))
+    f[~oc.interior_mask(grid)] = 0
+    omega = _best_omega(grid, c2, np.linspace(6.0, 14.0, 17))
+    tp = oc.time_params(grid, c2, omega)
+    sol, info = oc.cg(grid, c2, f, tp, rtol=1e-13, maxit=3000)
+    assert info["rel_res"] <= 1e-12
+    U = cf.dhs_direct(grid, c2, f, omega)
+    assert _rel(sol, U) < 1e-10
+
+
+def test_filter_function_bounded_by_one():
+    """beta_d <= 1 on the whole range of lambda~ an explicit step can produce,
+    with equality only at omega_e: A = I - S_h is positive semi-definite."""
+    for (n, order, c2max, om, Np) in [(2048, 4, 2.0, 200.0, 1), (128, 2, 1.0, 10.3, 1), (64, 4, 1.0, 3.7, 2)]:
+        grid = oc.Grid(2, (n, n), order)
+        tp = oc.time_params(grid, c2max, om, periods=Np)
+        lt = np.linspace(0.0, math.pi / tp["dt"] * (1 - 1e-9), 400001)
+        b = cf.beta_d_tp(lt, tp)
+        assert b.max() <= 1.0 + 1e-12
+        assert b.min() >= -0.5 - 1e-12
+        far = np.abs(lt - tp["omega_e"]) > 0.05 * tp["omega_e"]
+        assert b[far].max() < 0.999
+
+
 def test_fpi_converges_to_closed_form_dhs():
     """Far from resonance the plain fixed-point iteration itself reaches the DHS."""
     grid = oc.Grid(2, (12, 12), 4)
