@@ -249,11 +249,21 @@ WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *o
 /* Tuning of the time-stepping kernels.  kblock = leapfrog steps fused per
  * pass over the grid: 0 = automatic, 1 = one kernel launch per step, 2..4 =
  * temporally blocked passes (2-D grids; 3-D grids always take one step per
- * launch).  tile_x, tile_y are reserved and must be 0 (the blocked kernel's
- * tile is fixed by the precision, the order and kblock).  Every setting
- * evaluates the same expression per node and step; results agree with each
- * other to rounding. */
+ * launch).  tile_x must be 0 (or 64: a wavefront's columns).  tile_y = rows of
+ * the region a work-group loads (0 = automatic; FP64: 32, 64 or 128, FP32: 96
+ * or 192), i.e. the tile height including the halo of kblock * p/2 rows on
+ * each side.  Every setting evaluates the same expression per node and step;
+ * results agree with each other to rounding. */
 WH_API wh_status wh_set_tuning(wh_ctx *ctx, int32_t kblock, int32_t tile_x, int32_t tile_y);
+
+/* Autotuner: time `applies` applications (A v on a zero vector) with HIP
+ * events for every supported (kblock, tile_y) pair of the current grid,
+ * precision and order, keep the fastest as the context's tuning, and return
+ * it (outputs nullable; ms_per_apply = its mean time).  Requires the grid,
+ * workspace, c^2 and frequency; overwrites the workspace's scratch vectors
+ * (not c^2, f or the Krylov basis).  Synchronises the stream. */
+WH_API wh_status wh_autotune(wh_ctx *ctx, int32_t applies, int32_t *kblock, int32_t *tile_y,
+                             double *ms_per_apply);
 
 /* Current tuning after automatic choices have been resolved for this grid:
  * steps per pass and the owned tile of one work-group in nodes. */

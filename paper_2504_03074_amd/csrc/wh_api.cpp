@@ -277,7 +277,12 @@ int steps_per_pass(const wh_ctx *c) {
   if (c->dim != 2) return 1;
   if (c->kblock == 1) return 1;
   if (c->kblock >= 2) return c->kblock;
-  return 4;  // automatic choice for 2-D grids
+  return c->prec == WH_FP32_STATE ? 3 : 4;  // fastest on MI355X for 2048^2 (see the design notes)
+}
+
+// Tile height (rows of the loaded region) of the blocked kernel.
+int block_rows(const wh_ctx *c) {
+  return c->tile_y > 0 ? c->tile_y : wh::block_default_rows(c->prec == WH_FP32_STATE);
 }
 
 // One WaveHoltz application.  mode: ACCUMULATE (acc keeps the filter),
@@ -328,8 +333,8 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
         coef.wn[s] = c->wts[(size_t)n + 1];
       }
       const int m = (done + ks == total) ? mode : wh::ACCUMULATE;
-      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
-                                          c->stream));
+      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, block_rows(c), ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v,
+                                          out, c->stream));
       std::swap(ip, op);
       std::swap(ic, oc);
       done += ks;
@@ -743,9 +748,16 @@ wh_status wh_set_tuning(wh_ctx *c, int32_t kblock, int32_t tile_x, int32_t tile_
   WH_TRY(need(c, true, false, false, false, false));
   if (kblock < 0 || kblock > wh::kMaxBlockSteps)
     return fail(c, WH_EINVAL, "kblock must be in 0..%d", wh::kMaxBlockSteps);
-  if (tile_x != 0 || tile_y != 0) return fail(c, WH_EINVAL, "tile_x and tile_y are reserved and must be 0");
+  if (tile_x != 0 && tile_x != 64) return fail(c, WH_EINVAL, "tile_x must be 0 or 64");
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  if (tile_y != 0) {
+    const int K = kblock == 0 ? 4 : kblock;
+    if (c->dim != 2 || K < 2 || !wh::block_config_supported(fp32, c->order, K, tile_y))
+      return fail(c, WH_EINVAL, "tile_y = %d is not a supported tile height for this grid, precision and kblock",
+                  tile_y);
+  }
   c->kblock = kblock;
-  c->tile_x = tile_x;
+  c->tile_x = 0;
   c->tile_y = tile_y;
   return WH_OK;
 }
@@ -756,11 +768,73 @@ wh_status wh_get_tuning(const wh_ctx *c, int32_t *kblock, int32_t *tile_x, int32
   const int K = steps_per_pass(c);
   *kblock = K;
   if (K >= 2) {
-    wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, K, tile_x, tile_y);
+    wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, K, block_rows(c), tile_x, tile_y);
   } else {
     *tile_x = 64;
     *tile_y = 4;
   }
+  return WH_OK;
+}
+
+wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kblock, int32_t *tile_y, double *ms_per_apply) {
+  WH_TRY(need(c, true, true, true, false, true));
+  if (applies < 1 || applies > 100) return fail(c, WH_EINVAL, "applies must be in 1..100");
+  WH_TRY(set_device(c));
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  struct Cand {
+    int k, rows;
+  };
+  std::vector<Cand> cands{{1, 0}};
+  if (c->dim == 2) {
+    const int rows_list[] = {32, 64, 128, 96, 192};
+    for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
+      for (int rows : rows_list)
+        if (wh::block_config_supported(fp32, c->order, k, rows)) cands.push_back({k, rows});
+  }
+  const int saved_k = c->kblock, saved_rows = c->tile_y;
+  const bool saved_prof = c->profiling;
+  c->profiling = false;
+  hipEvent_t e0, e1;
+  WH_HIP(c, hipEventCreate(&e0));
+  WH_HIP(c, hipEventCreate(&e1));
+  double best_ms = INFINITY;
+  Cand best = cands[0];
+  wh_status st = WH_OK;
+  // v = 0 (values do not change the timing of the stencil arithmetic)
+  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
+  for (const Cand &cd : cands) {
+    c->kblock = cd.k;
+    c->tile_y = cd.rows;
+    st = apply_impl(c, c->tmp, false, wh::FINAL_A, c->b, nullptr);  // warm-up
+    if (st != WH_OK) break;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, WH_EDEVICE, "hipEventRecord failed"); break; }
+    for (int a = 0; a < applies && st == WH_OK; ++a) st = apply_impl(c, c->tmp, false, wh::FINAL_A, c->b, nullptr);
+    if (st != WH_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(c, WH_EDEVICE, "event timing failed");
+      break;
+    }
+    const double per = ms / applies;
+    if (per < best_ms) {
+      best_ms = per;
+      best = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->profiling = saved_prof;
+  if (st != WH_OK) {
+    c->kblock = saved_k;
+    c->tile_y = saved_rows;
+    return st;
+  }
+  c->kblock = best.k;
+  c->tile_y = best.rows;
+  if (kblock) *kblock = best.k;
+  if (tile_y) *tile_y = best.rows;
+  if (ms_per_apply) *ms_per_apply = best_ms;
   return WH_OK;
 }
 

@@ -223,54 +223,77 @@ hipError_t launch_typed(const StepGeom &g, int ksteps, const void *in_prev, cons
   return hipGetLastError();
 }
 
-// Rows per lane and waves per work-group.  FP64 keeps 8 rows per lane (the
-// register arrays stay in VGPRs) in 16 waves; FP32 keeps 24 rows in 8 waves.
+// Rows per lane: FP64 keeps 8 rows per lane and FP32 24 (larger register
+// arrays are not promoted to VGPRs).  Waves per work-group (NW) set the tile
+// height NW * RS; smaller groups let two groups share a CU so that one
+// group's loads overlap the other's arithmetic.
 template <typename T>
-struct BlockShape;
-template <>
-struct BlockShape<double> {
-  static constexpr int RS = 8, NW = 16;
-};
-template <>
-struct BlockShape<float> {
-  static constexpr int RS = 24, NW = 8;
+struct RowsPerLane {
+  static constexpr int RS = sizeof(T) == 8 ? 8 : 24;
 };
 
+template <typename T, int P, int K>
+hipError_t dispatch_nw(const StepGeom &g, int nw, int ksteps, const void *ip, const void *ic, void *op, void *oc,
+                       double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode, const double *v,
+                       double *out, hipStream_t s) {
+  constexpr int RS = RowsPerLane<T>::RS;
+  switch (nw) {
+    case 4: return launch_typed<T, P, K, RS, 4>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 8: return launch_typed<T, P, K, RS, 8>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 16:
+      // FP32's 24-row arrays do not fit 1024-thread groups without spilling
+      if constexpr (sizeof(T) == 8)
+        return launch_typed<T, P, K, RS, 16>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int P>
-hipError_t dispatch_k(const StepGeom &g, int K, int ksteps, const void *ip, const void *ic, void *op, void *oc,
-                      double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode, const double *v,
-                      double *out, hipStream_t s) {
-  constexpr int RS = BlockShape<T>::RS, NW = BlockShape<T>::NW;
+hipError_t dispatch_k(const StepGeom &g, int K, int nw, int ksteps, const void *ip, const void *ic, void *op,
+                      void *oc, double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
+                      const double *v, double *out, hipStream_t s) {
   switch (K) {
-    case 2: return launch_typed<T, P, 2, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
-    case 3: return launch_typed<T, P, 3, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
-    case 4: return launch_typed<T, P, 4, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 2: return dispatch_nw<T, P, 2>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 3: return dispatch_nw<T, P, 3>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 4: return dispatch_nw<T, P, 4>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-bool block_config_supported(int order, int K) { return (order == 2 || order == 4) && K >= 2 && K <= kMaxBlockSteps; }
-
-void block_tile_shape(bool fp32, int order, int K, int *owned_x, int *owned_y) {
-  const int H = K * (order / 2);
-  *owned_x = 64 - 2 * H;
-  *owned_y = fp32 ? BlockShape<float>::RS * BlockShape<float>::NW - 2 * H
-                  : BlockShape<double>::RS * BlockShape<double>::NW - 2 * H;
+bool block_config_supported(bool fp32, int order, int K, int rows) {
+  if (!(order == 2 || order == 4) || K < 2 || K > kMaxBlockSteps) return false;
+  const int rs = fp32 ? RowsPerLane<float>::RS : RowsPerLane<double>::RS;
+  if (rows % rs != 0) return false;
+  const int nw = rows / rs;
+  if (nw != 4 && nw != 8 && !(nw == 16 && !fp32)) return false;
+  return rows - 2 * K * (order / 2) > 0;
 }
 
-hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int ksteps, const void *in_prev,
+int block_default_rows(bool fp32) { return fp32 ? 4 * RowsPerLane<float>::RS : 8 * RowsPerLane<double>::RS; }
+
+void block_tile_shape(bool fp32, int order, int K, int rows, int *owned_x, int *owned_y) {
+  const int H = K * (order / 2);
+  *owned_x = 64 - 2 * H;
+  *owned_y = rows - 2 * H;
+}
+
+hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, int ksteps, const void *in_prev,
                                  const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
                                  const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
                                  hipStream_t s) {
-  if (ksteps < 1 || ksteps > K || !block_config_supported(g.order, K)) return hipErrorInvalidValue;
+  if (ksteps < 1 || ksteps > K || !block_config_supported(fp32, g.order, K, rows)) return hipErrorInvalidValue;
+  const int nw = rows / (fp32 ? RowsPerLane<float>::RS : RowsPerLane<double>::RS);
   if (fp32) {
-    if (g.order == 2) return dispatch_k<float, 2>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
-    return dispatch_k<float, 4>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+    if (g.order == 2)
+      return dispatch_k<float, 2>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+    return dispatch_k<float, 4>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
   }
-  if (g.order == 2) return dispatch_k<double, 2>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
-  return dispatch_k<double, 4>(g, K, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+  if (g.order == 2)
+    return dispatch_k<double, 2>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+  return dispatch_k<double, 4>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
 }
 
 }  // namespace wh

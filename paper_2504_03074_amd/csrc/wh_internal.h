@@ -49,13 +49,16 @@ struct BlockCoef {
   double gn[kMaxBlockSteps];
   double wn[kMaxBlockSteps];
 };
-hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int ksteps, const void *in_prev,
+hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, int ksteps, const void *in_prev,
                                  const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
                                  const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
                                  hipStream_t s);
-bool block_config_supported(int order, int K);
+// rows = tile height of the loaded region (waves per group x rows per lane):
+// FP64 32, 64 or 128; FP32 96 or 192.
+bool block_config_supported(bool fp32, int order, int K, int rows);
+int block_default_rows(bool fp32);
 // Owned tile (nodes) of one work-group of the blocked kernel.
-void block_tile_shape(bool fp32, int order, int K, int *owned_x, int *owned_y);
+void block_tile_shape(bool fp32, int order, int K, int rows, int *owned_x, int *owned_y);
 
 // Convert/copy helpers.
 hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s);

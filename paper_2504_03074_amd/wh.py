@@ -105,6 +105,8 @@ def _load():
         "wh_get_tuning": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32)]),
         "wh_profile_enable": (st, [_vp, ctypes.c_int32]),
+        "wh_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_double)]),
         "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
     }
     for name, (res, args) in sig.items():
@@ -254,6 +256,12 @@ def wh_get_tuning(ctx):
     return int(k.value), int(tx.value), int(ty.value)
 
 
+def wh_autotune(ctx, applies=3):
+    k, rows, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(ctx, _load().wh_autotune(ctx, int(applies), ctypes.byref(k), ctypes.byref(rows), ctypes.byref(ms)))
+    return int(k.value), int(rows.value), float(ms.value)
+
+
 def wh_profile_enable(ctx, enable=True):
     _check(ctx, _load().wh_profile_enable(ctx, int(bool(enable))))
 
@@ -352,6 +360,11 @@ class Solver:
 
     def tuning(self):
         return wh_get_tuning(self.ctx)
+
+    def autotune(self, applies=3):
+        """Time every kernel variant on this problem and keep the fastest:
+        returns (steps per pass, tile rows, ms per application)."""
+        return wh_autotune(self.ctx, applies)
 
     def apply(self, v, with_forcing=True, out=None):
         out = self.new() if out is None else out

@@ -147,6 +147,39 @@ def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods
     assert _walls_zero(fin.cpu().numpy())
 
 
+@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 128), ("fp32", 96), ("fp32", 192)])
+@pytest.mark.parametrize("kblock", [2, 4])
+def test_blocked_tile_heights(torch, prec, rows, kblock):
+    """Every work-group height of the blocked kernel against the oracle."""
+    _say(f"[tile rows] {prec} rows={rows} k={kblock}")
+    grid, c2, f, v = _problem(2, (173, 211), 4, "var", seed=401)
+    s = _solver(2, (173, 211), 4, prec)
+    s.set_tuning(kblock, 0, rows)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(37.0)
+    tp = oc.time_params(grid, c2, 37.0)
+    got = s.apply(_to_dev(torch, v), with_forcing=True).cpu().numpy()
+    assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
+    assert _walls_zero(got)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_keeps_results(torch, prec):
+    _say(f"[autotune] {prec}")
+    grid, c2, f, v = _problem(2, (300, 257), 2, "var", seed=411)
+    s = _solver(2, (300, 257), 2, prec)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(44.0)
+    k, rows, ms = s.autotune(2)
+    assert 1 <= k <= 4 and ms > 0
+    assert s.tuning()[0] == k
+    tp = oc.time_params(grid, c2, 44.0)
+    got = s.apply(_to_dev(torch, v), with_forcing=True).cpu().numpy()
+    assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_run_periods_final_state_and_filter(torch, prec):
     _say(f"[run_periods] {prec}")
