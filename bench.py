@@ -49,7 +49,10 @@ def parse():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=40000)
-    ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per pass (0 = automatic)")
+    ap.add_argument("--kernel", default="auto", help="time-stepping kernel family (auto, node, blocked_2d)")
+    ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
+    ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
+    ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
     ap.add_argument("--mode", choices=["solve", "kernel", "copy"], default="solve")
     ap.add_argument("--applies", type=int, default=20, help="applications timed in --mode kernel")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
@@ -65,13 +68,14 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "block_steps_kernel_square2048_
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_03074_amd", "csrc", "wh_block.hip")
 
 
-def measured_traffic(n, precision, kblock):
+def measured_traffic(n, precision, tun):
     """HBM bytes per launch of the blocked kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
     the workload differs from the one profiled or the kernel source changed
     since the counters were taken."""
     import hashlib
-    if not (n == 2048 and precision == "fp64" and kblock == 4) or not os.path.exists(COUNTER_SUMMARY):
+    profiled = tun["kernel"] == "blocked_2d" and tun["kblock"] == 4 and tun["tile"] == 64
+    if not (n == 2048 and precision == "fp64" and profiled) or not os.path.exists(COUNTER_SUMMARY):
         return None
     fields = {}
     for line in open(COUNTER_SUMMARY):
@@ -144,12 +148,16 @@ def main():
     log(f"inputs generated in {time.perf_counter() - t_setup:.1f}s")
     s = Solver(2, (args.n, args.n), order=order, precision=args.precision,
                restart=args.restart if args.solver == "gmres" else 2)
-    s.set_tuning(args.kblock)
+    s.set_tuning(args.kernel, args.kblock, args.tile)
     s.set_c2(w["c2"])
     s.set_source(w["f"])
     tp = s.set_frequency(w["omega"])
-    kblock, tile_x, tile_y = s.tuning()
-    log(f"time params {tp}, steps/pass {kblock}, tile {tile_x}x{tile_y}")
+    if args.autotune:
+        log(f"autotune: {s.autotune(3)}")
+    tun = s.tuning()
+    kblock = tun["kblock"]
+    tile_x, tile_y = tun["owned"]
+    log(f"time params {tp}, tuning {tun}")
     unknowns = (args.n - 1) ** 2
     pts_per_apply = unknowns * tp["nt"] * tp["periods"]
 
@@ -207,7 +215,7 @@ def main():
     launch_us = prof["ms"] / prof["launches"] * 1e3
     bytes_per_launch = prof["bytes"] / prof["launches"]
     achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
-    kname = "block_steps_kernel" if kblock >= 2 else "step_kernel"
+    kname = {"blocked_2d": "block_steps_kernel", "node": "step_kernel"}.get(tun["kernel"], tun["kernel"])
 
     result = {
         "metric": "grid-pt updates/s (GPts/s, % HBM roofline) + time to Helmholtz residual 1e-8",
@@ -228,8 +236,8 @@ def main():
                         + f" to {args.rtol:g}",
             "n": args.n, "order": order, "omega": w["omega"], "nt": tp["nt"], "solver": args.solver,
             "restart": args.restart if args.solver == "gmres" else None,
-            "rtol": args.rtol, "precision": args.precision, "steps_per_pass": kblock,
-            "tile": [tile_x, tile_y],
+            "rtol": args.rtol, "precision": args.precision, "kernel": tun["kernel"], "steps_per_launch": kblock,
+            "tile_rows": tun["tile"], "owned_tile": [tile_x, tile_y],
         },
         "time_to_residual_s": round(elapsed / args.steps, 4),
         "converged": all(i["converged"] for i in infos),
@@ -245,7 +253,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.n, args.precision, kblock),
+            "traffic": measured_traffic(args.n, args.precision, tun),
             "bytes_per_launch": bytes_per_launch,
             "launch_us": round(launch_us, 3),
             "launches": prof["launches"],

@@ -246,28 +246,43 @@ WH_API wh_status wh_helmholtz_residual(wh_ctx *ctx, const double *u, double *res
  * library's deterministic reduction order.  Synchronises the stream. */
 WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *out);
 
-/* Tuning of the time-stepping kernels.  kblock = leapfrog steps fused per
- * pass over the grid: 0 = automatic, 1 = one kernel launch per step, 2..4 =
- * temporally blocked passes (2-D grids; 3-D grids always take one step per
- * launch).  tile_x must be 0 (or 64: a wavefront's columns).  tile_y = rows of
- * the region a work-group loads (0 = automatic; FP64: 32, 64 or 128, FP32: 96
- * or 192), i.e. the tile height including the halo of kblock * p/2 rows on
- * each side.  Every setting evaluates the same expression per node and step;
- * results agree with each other to rounding. */
-WH_API wh_status wh_set_tuning(wh_ctx *ctx, int32_t kblock, int32_t tile_x, int32_t tile_y);
+/* Time-stepping kernel families.
+ *   WH_KERNEL_AUTO       library choice (2-D: blocked, 4 steps per pass in
+ *                        FP64 and 3 in FP32; 3-D: one node per thread)
+ *   WH_KERNEL_NODE       one node per thread, one step per launch (2-D, 3-D)
+ *   WH_KERNEL_BLOCKED_2D kblock = 2..4 steps per launch; tile = rows of the
+ *                        region a work-group loads (FP64: 32, 64, 128;
+ *                        FP32: 96, 192; 0 = default), halo kblock*p/2 included
+ *   WH_KERNEL_ZCOL_3D    one step per launch; tile = consecutive z nodes per
+ *                        thread (4, 8, 16), z-neighbours kept in registers
+ * Every family evaluates the same expression per node and step; results
+ * agree with each other to rounding. */
+typedef enum {
+  WH_KERNEL_AUTO = 0,
+  WH_KERNEL_NODE = 1,
+  WH_KERNEL_BLOCKED_2D = 2,
+  WH_KERNEL_ZCOL_3D = 3
+} wh_kernel;
+
+/* Select the kernel family, steps per launch and tile parameter (see
+ * wh_kernel).  WH_EINVAL for combinations the grid, order or precision do
+ * not support. */
+WH_API wh_status wh_set_tuning(wh_ctx *ctx, int32_t kernel, int32_t kblock, int32_t tile);
 
 /* Autotuner: time `applies` applications (A v on a zero vector) with HIP
- * events for every supported (kblock, tile_y) pair of the current grid,
- * precision and order, keep the fastest as the context's tuning, and return
- * it (outputs nullable; ms_per_apply = its mean time).  Requires the grid,
- * workspace, c^2 and frequency; overwrites the workspace's scratch vectors
- * (not c^2, f or the Krylov basis).  Synchronises the stream. */
-WH_API wh_status wh_autotune(wh_ctx *ctx, int32_t applies, int32_t *kblock, int32_t *tile_y,
+ * events for every supported (kernel, kblock, tile) choice of the current
+ * grid, precision and order, keep the fastest as the context's tuning, and
+ * return it (outputs nullable; ms_per_apply = its mean time).  Requires the
+ * grid, workspace, c^2 and frequency; overwrites the workspace's scratch
+ * vectors (not c^2, f or the Krylov basis).  Synchronises the stream. */
+WH_API wh_status wh_autotune(wh_ctx *ctx, int32_t applies, int32_t *kernel, int32_t *kblock, int32_t *tile,
                              double *ms_per_apply);
 
-/* Current tuning after automatic choices have been resolved for this grid:
- * steps per pass and the owned tile of one work-group in nodes. */
-WH_API wh_status wh_get_tuning(const wh_ctx *ctx, int32_t *kblock, int32_t *tile_x, int32_t *tile_y);
+/* Current tuning after automatic choices are resolved: kernel family,
+ * steps per launch, tile parameter, and the owned tile of one work-group
+ * (owned_x, owned_y nodes; nullable outputs). */
+WH_API wh_status wh_get_tuning(const wh_ctx *ctx, int32_t *kernel, int32_t *kblock, int32_t *tile,
+                               int32_t *owned_x, int32_t *owned_y);
 
 /* Timing of the time-stepping kernels, measured with HIP events recorded on
  * the context's stream around the leapfrog launches of every application

@@ -46,7 +46,7 @@ struct wh_ctx {
   std::vector<double> wts;   // filter weight of level n, n = 0..N
   std::vector<double> frc;   // -dt^2 cos(omega_e t^n), n = 0..N-1
 
-  int kblock = 0, tile_x = 0, tile_y = 0;
+  int kernel = WH_KERNEL_AUTO, kblock = 0, tile = 0;
   double *pinned = nullptr;  // host staging for reduction results
   size_t pinned_count = 0;
 
@@ -272,17 +272,34 @@ wh_status drain_profile(wh_ctx *c) {
   return WH_OK;
 }
 
-// Leapfrog steps fused per pass for the current grid (1 = the per-step kernel).
-int steps_per_pass(const wh_ctx *c) {
-  if (c->dim != 2) return 1;
-  if (c->kblock == 1) return 1;
-  if (c->kblock >= 2) return c->kblock;
-  return c->prec == WH_FP32_STATE ? 3 : 4;  // fastest on MI355X for 2048^2 (see the design notes)
+struct Tuning {
+  int kernel, kblock, tile;
+};
+
+// The kernel family, steps per launch and tile parameter actually used.
+Tuning resolve_tuning(const wh_ctx *c) {
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  if (c->kernel == WH_KERNEL_AUTO) {
+    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, fp32 ? 3 : 4, wh::block_default_rows(fp32)};
+    return {WH_KERNEL_NODE, 1, 0};
+  }
+  if (c->kernel == WH_KERNEL_BLOCKED_2D)
+    return {c->kernel, c->kblock, c->tile > 0 ? c->tile : wh::block_default_rows(fp32)};
+  if (c->kernel == WH_KERNEL_ZCOL_3D) return {c->kernel, 1, c->tile > 0 ? c->tile : 8};
+  return {WH_KERNEL_NODE, 1, 0};
 }
 
-// Tile height (rows of the loaded region) of the blocked kernel.
-int block_rows(const wh_ctx *c) {
-  return c->tile_y > 0 ? c->tile_y : wh::block_default_rows(c->prec == WH_FP32_STATE);
+bool tuning_supported(const wh_ctx *c, int kernel, int kblock, int tile) {
+  const bool fp32 = c->prec == WH_FP32_STATE;
+  switch (kernel) {
+    case WH_KERNEL_AUTO: return kblock == 0 && tile == 0;
+    case WH_KERNEL_NODE: return kblock <= 1 && tile == 0;
+    case WH_KERNEL_BLOCKED_2D:
+      return c->dim == 2 && kblock >= 2 && kblock <= wh::kMaxBlockSteps &&
+             (tile == 0 || wh::block_config_supported(fp32, c->order, kblock, tile));
+    case WH_KERNEL_ZCOL_3D: return c->dim == 3 && kblock <= 1 && (tile == 0 || wh::zcol_supported(tile));
+    default: return false;
+  }
 }
 
 // One WaveHoltz application.  mode: ACCUMULATE (acc keeps the filter),
@@ -302,7 +319,8 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
     WH_TRY(take_events(c, &ev0, &ev1));
     WH_HIP(c, hipEventRecord(ev0, c->stream));
   }
-  const int K = steps_per_pass(c);
+  const Tuning tu = resolve_tuning(c);
+  const int K = tu.kernel == WH_KERNEL_BLOCKED_2D ? tu.kblock : 1;
   const double T = (double)state_bytes(c);
   const double aux = (c2 ? T : 0.0) + (f ? T : 0.0);  // c^2 and f reads per node and launch
   int64_t launches = 0;
@@ -313,8 +331,13 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
     cur = c->W[1];
     for (int64_t n = 1; n < N; ++n) {
       const int m = (n == N - 1) ? mode : wh::ACCUMULATE;
-      WH_HIP(c, wh::launch_step(fp32, g, cur, prev, c->acc, c2, f, forcing ? c->frc[(size_t)n] : 0.0,
-                                c->wts[(size_t)n + 1], m, v, out, c->stream));
+      if (tu.kernel == WH_KERNEL_ZCOL_3D)
+        WH_HIP(c, wh::launch_step3d_zcol(fp32, g, tu.tile, cur, prev, c->acc, c2, f,
+                                         forcing ? c->frc[(size_t)n] : 0.0, c->wts[(size_t)n + 1], m, v, out,
+                                         c->stream));
+      else
+        WH_HIP(c, wh::launch_step(fp32, g, cur, prev, c->acc, c2, f, forcing ? c->frc[(size_t)n] : 0.0,
+                                  c->wts[(size_t)n + 1], m, v, out, c->stream));
       std::swap(prev, cur);
       ++launches;
       // W^n, W^{n-1} read, W^{n+1} written, accumulator read and written
@@ -333,8 +356,8 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
         coef.wn[s] = c->wts[(size_t)n + 1];
       }
       const int m = (done + ks == total) ? mode : wh::ACCUMULATE;
-      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, block_rows(c), ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v,
-                                          out, c->stream));
+      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, tu.tile, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
+                                          c->stream));
       std::swap(ip, op);
       std::swap(ic, oc);
       done += ks;
@@ -550,7 +573,8 @@ wh_status wh_set_grid(wh_ctx *c, int32_t dim, const int64_t n[3], int32_t order,
   c->ws_bytes = 0;
   c->c2_set = c->f_set = c->freq_set = false;
   c->c2_is_const = false;
-  c->kblock = c->tile_x = c->tile_y = 0;
+  c->kernel = WH_KERNEL_AUTO;
+  c->kblock = c->tile = 0;
   c->err.clear();
   return WH_OK;
 }
@@ -744,70 +768,72 @@ wh_status wh_helmholtz_residual(wh_ctx *c, const double *u, double *res, double 
   return WH_OK;
 }
 
-wh_status wh_set_tuning(wh_ctx *c, int32_t kblock, int32_t tile_x, int32_t tile_y) {
+wh_status wh_set_tuning(wh_ctx *c, int32_t kernel, int32_t kblock, int32_t tile) {
   WH_TRY(need(c, true, false, false, false, false));
-  if (kblock < 0 || kblock > wh::kMaxBlockSteps)
-    return fail(c, WH_EINVAL, "kblock must be in 0..%d", wh::kMaxBlockSteps);
-  if (tile_x != 0 && tile_x != 64) return fail(c, WH_EINVAL, "tile_x must be 0 or 64");
-  const bool fp32 = c->prec == WH_FP32_STATE;
-  if (tile_y != 0) {
-    const int K = kblock == 0 ? 4 : kblock;
-    if (c->dim != 2 || K < 2 || !wh::block_config_supported(fp32, c->order, K, tile_y))
-      return fail(c, WH_EINVAL, "tile_y = %d is not a supported tile height for this grid, precision and kblock",
-                  tile_y);
-  }
+  if (!tuning_supported(c, kernel, kblock, tile))
+    return fail(c, WH_EINVAL, "kernel %d with kblock %d and tile %d is not supported for this grid, order and precision",
+                kernel, kblock, tile);
+  c->kernel = kernel;
   c->kblock = kblock;
-  c->tile_x = 0;
-  c->tile_y = tile_y;
+  c->tile = tile;
   return WH_OK;
 }
 
-wh_status wh_get_tuning(const wh_ctx *c, int32_t *kblock, int32_t *tile_x, int32_t *tile_y) {
-  if (!c || !kblock || !tile_x || !tile_y) return WH_EINVAL;
+wh_status wh_get_tuning(const wh_ctx *c, int32_t *kernel, int32_t *kblock, int32_t *tile, int32_t *owned_x,
+                        int32_t *owned_y) {
+  if (!c) return WH_EINVAL;
   if (!c->grid_set) return WH_ESTATE;
-  const int K = steps_per_pass(c);
-  *kblock = K;
-  if (K >= 2) {
-    wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, K, block_rows(c), tile_x, tile_y);
-  } else {
-    *tile_x = 64;
-    *tile_y = 4;
+  const Tuning tu = resolve_tuning(c);
+  int ox = 64, oy = 4;
+  const int r = c->order / 2;
+  if (tu.kernel == WH_KERNEL_BLOCKED_2D) {
+    wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, tu.kblock, tu.tile, &ox, &oy);
+  } else if (tu.kernel == WH_KERNEL_ZCOL_3D) {
+    oy = 4;
   }
+  (void)r;
+  if (kernel) *kernel = tu.kernel;
+  if (kblock) *kblock = tu.kblock;
+  if (tile) *tile = tu.tile;
+  if (owned_x) *owned_x = ox;
+  if (owned_y) *owned_y = oy;
   return WH_OK;
 }
 
-wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kblock, int32_t *tile_y, double *ms_per_apply) {
+wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblock, int32_t *tile,
+                      double *ms_per_apply) {
   WH_TRY(need(c, true, true, true, false, true));
   if (applies < 1 || applies > 100) return fail(c, WH_EINVAL, "applies must be in 1..100");
   WH_TRY(set_device(c));
-  const bool fp32 = c->prec == WH_FP32_STATE;
-  struct Cand {
-    int k, rows;
-  };
-  std::vector<Cand> cands{{1, 0}};
-  if (c->dim == 2) {
-    const int rows_list[] = {32, 64, 128, 96, 192};
+  std::vector<Tuning> cands{{WH_KERNEL_NODE, 1, 0}};
+  if (c->dim == 3) {
+    for (int zb : {4, 8, 16}) cands.push_back({WH_KERNEL_ZCOL_3D, 1, zb});
+  } else {
     for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
-      for (int rows : rows_list)
-        if (wh::block_config_supported(fp32, c->order, k, rows)) cands.push_back({k, rows});
+      for (int rows : {32, 64, 128, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
   }
-  const int saved_k = c->kblock, saved_rows = c->tile_y;
+  const Tuning saved{c->kernel, c->kblock, c->tile};
   const bool saved_prof = c->profiling;
   c->profiling = false;
   hipEvent_t e0, e1;
   WH_HIP(c, hipEventCreate(&e0));
   WH_HIP(c, hipEventCreate(&e1));
   double best_ms = INFINITY;
-  Cand best = cands[0];
+  Tuning best = cands[0];
   wh_status st = WH_OK;
   // v = 0 (values do not change the timing of the stencil arithmetic)
   WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
-  for (const Cand &cd : cands) {
-    c->kblock = cd.k;
-    c->tile_y = cd.rows;
+  for (const Tuning &cd : cands) {
+    if (!tuning_supported(c, cd.kernel, cd.kblock, cd.tile)) continue;
+    c->kernel = cd.kernel;
+    c->kblock = cd.kblock;
+    c->tile = cd.tile;
     st = apply_impl(c, c->tmp, false, wh::FINAL_A, c->b, nullptr);  // warm-up
     if (st != WH_OK) break;
-    if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, WH_EDEVICE, "hipEventRecord failed"); break; }
+    if (hipEventRecord(e0, c->stream) != hipSuccess) {
+      st = fail(c, WH_EDEVICE, "hipEventRecord failed");
+      break;
+    }
     for (int a = 0; a < applies && st == WH_OK; ++a) st = apply_impl(c, c->tmp, false, wh::FINAL_A, c->b, nullptr);
     if (st != WH_OK) break;
     float ms = 0.0f;
@@ -826,14 +852,17 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kblock, int32_t *tile
   (void)hipEventDestroy(e1);
   c->profiling = saved_prof;
   if (st != WH_OK) {
-    c->kblock = saved_k;
-    c->tile_y = saved_rows;
+    c->kernel = saved.kernel;
+    c->kblock = saved.kblock;
+    c->tile = saved.tile;
     return st;
   }
-  c->kblock = best.k;
-  c->tile_y = best.rows;
-  if (kblock) *kblock = best.k;
-  if (tile_y) *tile_y = best.rows;
+  c->kernel = best.kernel;
+  c->kblock = best.kblock;
+  c->tile = best.tile;
+  if (kernel) *kernel = best.kernel;
+  if (kblock) *kblock = best.kblock;
+  if (tile) *tile = best.tile;
   if (ms_per_apply) *ms_per_apply = best_ms;
   return WH_OK;
 }

@@ -60,6 +60,13 @@ int block_default_rows(bool fp32);
 // Owned tile (nodes) of one work-group of the blocked kernel.
 void block_tile_shape(bool fp32, int order, int K, int rows, int *owned_x, int *owned_y);
 
+// One leapfrog step for a 3-D grid with zb consecutive z nodes per thread
+// (zb in {4, 8, 16}); same arguments and modes as launch_step.
+hipError_t launch_step3d_zcol(bool fp32, const StepGeom &g, int zb, const void *cur, void *prev_next, double *acc,
+                              const void *c2, const void *f, double gn, double wn, int mode, const double *v,
+                              double *out, hipStream_t s);
+bool zcol_supported(int zb);
+
 // Convert/copy helpers.
 hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s);
 hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n, hipStream_t s);

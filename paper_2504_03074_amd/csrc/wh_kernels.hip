@@ -170,6 +170,76 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void step_kernel(
   }
 }
 
+// 3-D step with z coarsening: thread (i, j) updates nodes k0..k0+ZB-1 of its
+// column, keeping W^n along the column in registers so each z-neighbour is
+// loaded once per column segment instead of once per node; x- and
+// y-neighbours are loaded as in step_kernel.  Same arithmetic per node.
+template <typename T, int P, int ZB>
+__global__ __launch_bounds__(kBlockX *kBlockY) void step3d_zcol_kernel(
+    StepGeom g, const T *__restrict__ cur, T *__restrict__ prev_next, double *__restrict__ acc,
+    const T *__restrict__ c2, const T *__restrict__ f, double gn, double wn, int mode,
+    const double *__restrict__ v, double *__restrict__ out) {
+  constexpr int R = P / 2;
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k0 = blockIdx.z * ZB;
+  if (i > g.nx || j > g.ny) return;
+  const bool col_wall = i == 0 || i == g.nx || j == 0 || j == g.ny;
+  const int64_t base = (int64_t)i + (int64_t)j * g.sy;
+  // column of W^n for planes k0-R .. k0+ZB-1+R (odd reflection beyond the z walls)
+  T col[ZB + 2 * R];
+#pragma unroll
+  for (int t = 0; t < ZB + 2 * R; ++t) {
+    int k = k0 - R + t;
+    T sgn = T(1);
+    if (k < 0) { k = -k; sgn = -sgn; } else if (k > g.nz) { k = 2 * g.nz - k; sgn = -sgn; }
+    col[t] = (col_wall || k > g.nz) ? T(0) : sgn * cur[base + (int64_t)k * g.sz];
+  }
+  const Coef<T> c = coef_of<T>(g);
+#pragma unroll
+  for (int t = 0; t < ZB; ++t) {
+    const int k = k0 + t;
+    if (k > g.nz) break;
+    const int64_t idx = base + (int64_t)k * g.sz;
+    const bool wall = col_wall || k == 0 || k == g.nz;
+    if (wall) {
+      if (mode != ACCUMULATE) out[idx] = 0.0;
+      continue;
+    }
+    const T w0 = col[t + R];
+    T r;
+    if (P == 2) {
+      r = c.kx * (cur[idx - 1] + cur[idx + 1]) + c.ky * (cur[idx - g.sy] + cur[idx + g.sy]) +
+          c.kz * (col[t + R - 1] + col[t + R + 1]);
+    } else {
+      const bool near = (i < 2) || (i > g.nx - 2) || (j < 2) || (j > g.ny - 2);
+      T ax1, ax2, ay1, ay2;
+      if (!near) {
+        ax1 = cur[idx - 1] + cur[idx + 1];
+        ax2 = cur[idx - 2] + cur[idx + 2];
+        ay1 = cur[idx - g.sy] + cur[idx + g.sy];
+        ay2 = cur[idx - 2 * g.sy] + cur[idx + 2 * g.sy];
+      } else {
+        ax1 = load_reflect<T, 3>(cur, i - 1, j, k, g) + load_reflect<T, 3>(cur, i + 1, j, k, g);
+        ax2 = load_reflect<T, 3>(cur, i - 2, j, k, g) + load_reflect<T, 3>(cur, i + 2, j, k, g);
+        ay1 = load_reflect<T, 3>(cur, i, j - 1, k, g) + load_reflect<T, 3>(cur, i, j + 1, k, g);
+        ay2 = load_reflect<T, 3>(cur, i, j - 2, k, g) + load_reflect<T, 3>(cur, i, j + 2, k, g);
+      }
+      r = c.kx * (T(16) * ax1 - ax2) + c.ky * (T(16) * ay1 - ay2) +
+          c.kz * (T(16) * (col[t + R - 1] + col[t + R + 1]) - (col[t + R - 2] + col[t + R + 2]));
+    }
+    const T lap = r - c.kc * w0;
+    const T c2v = c2 ? c2[idx] : static_cast<T>(g.c2const);
+    T nxt = T(2) * w0 - prev_next[idx] + c2v * lap;
+    if (f) nxt += static_cast<T>(gn) * f[idx];
+    prev_next[idx] = nxt;
+    const double a = acc[idx] + wn * static_cast<double>(nxt);
+    if (mode == ACCUMULATE) acc[idx] = a;
+    else if (mode == FINAL_FILTER) out[idx] = a;
+    else out[idx] = v[idx] - a;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // conversions
 // ---------------------------------------------------------------------------
@@ -445,6 +515,42 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
   if (fp32) dispatch_step<float>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
   else dispatch_step<double>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
   return hipGetLastError();
+}
+
+template <typename T, int P, int ZB>
+static void zcol_typed(const StepGeom &g, const void *cur, void *prev_next, double *acc, const void *c2,
+                       const void *f, double gn, double wn, int mode, const double *v, double *out, hipStream_t s) {
+  dim3 grid((unsigned)((g.nx + 1 + kBlockX - 1) / kBlockX), (unsigned)((g.ny + 1 + kBlockY - 1) / kBlockY),
+            (unsigned)((g.nz + 1 + ZB - 1) / ZB));
+  step3d_zcol_kernel<T, P, ZB><<<grid, dim3(kBlockX, kBlockY), 0, s>>>(
+      g, static_cast<const T *>(cur), static_cast<T *>(prev_next), acc, static_cast<const T *>(c2),
+      static_cast<const T *>(f), gn, wn, mode, v, out);
+}
+
+template <typename T, int P>
+static hipError_t zcol_zb(const StepGeom &g, int zb, const void *cur, void *prev_next, double *acc, const void *c2,
+                          const void *f, double gn, double wn, int mode, const double *v, double *out, hipStream_t s) {
+  switch (zb) {
+    case 4: zcol_typed<T, P, 4>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s); break;
+    case 8: zcol_typed<T, P, 8>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s); break;
+    case 16: zcol_typed<T, P, 16>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool zcol_supported(int zb) { return zb == 4 || zb == 8 || zb == 16; }
+
+hipError_t launch_step3d_zcol(bool fp32, const StepGeom &g, int zb, const void *cur, void *prev_next, double *acc,
+                              const void *c2, const void *f, double gn, double wn, int mode, const double *v,
+                              double *out, hipStream_t s) {
+  if (g.dim != 3 || !zcol_supported(zb)) return hipErrorInvalidValue;
+  if (fp32) {
+    if (g.order == 2) return zcol_zb<float, 2>(g, zb, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+    return zcol_zb<float, 4>(g, zb, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  }
+  if (g.order == 2) return zcol_zb<double, 2>(g, zb, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
+  return zcol_zb<double, 4>(g, zb, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
 }
 
 hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s) {

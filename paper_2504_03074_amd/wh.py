@@ -19,6 +19,9 @@ WH_OK, WH_EINVAL, WH_ENOMEM, WH_EDEVICE, WH_EUNSTABLE, WH_ENOTCONV, WH_ENONFINIT
 WH_FP64, WH_FP32_STATE = 0, 1
 WH_SOLVER_FPI, WH_SOLVER_GMRES, WH_SOLVER_CG = 0, 1, 2
 WH_MAX_RESTART = 4096
+WH_KERNEL_AUTO, WH_KERNEL_NODE, WH_KERNEL_BLOCKED_2D, WH_KERNEL_ZCOL_3D = 0, 1, 2, 3
+KERNEL_NAMES = {0: "auto", 1: "node", 2: "blocked_2d", 3: "zcol_3d"}
+KERNEL_IDS = {v: k for k, v in KERNEL_NAMES.items()}
 
 
 class WhError(RuntimeError):
@@ -103,10 +106,11 @@ def _load():
         "wh_dot": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "wh_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "wh_get_tuning": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32)]),
         "wh_profile_enable": (st, [_vp, ctypes.c_int32]),
         "wh_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                             ctypes.POINTER(ctypes.c_double)]),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
         "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
     }
     for name, (res, args) in sig.items():
@@ -246,20 +250,23 @@ def wh_dot(ctx, x: int, y: int) -> float:
     return float(out.value)
 
 
-def wh_set_tuning(ctx, kblock=0, tile_x=0, tile_y=0):
-    _check(ctx, _load().wh_set_tuning(ctx, int(kblock), int(tile_x), int(tile_y)))
+def wh_set_tuning(ctx, kernel=WH_KERNEL_AUTO, kblock=0, tile=0):
+    _check(ctx, _load().wh_set_tuning(ctx, int(kernel), int(kblock), int(tile)))
 
 
 def wh_get_tuning(ctx):
-    k, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(ctx, _load().wh_get_tuning(ctx, ctypes.byref(k), ctypes.byref(tx), ctypes.byref(ty)))
-    return int(k.value), int(tx.value), int(ty.value)
+    """(kernel, kblock, tile, owned_x, owned_y) actually used."""
+    out = [ctypes.c_int32() for _ in range(5)]
+    _check(ctx, _load().wh_get_tuning(ctx, *[ctypes.byref(o) for o in out]))
+    return tuple(int(o.value) for o in out)
 
 
 def wh_autotune(ctx, applies=3):
-    k, rows, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-    _check(ctx, _load().wh_autotune(ctx, int(applies), ctypes.byref(k), ctypes.byref(rows), ctypes.byref(ms)))
-    return int(k.value), int(rows.value), float(ms.value)
+    """(kernel, kblock, tile, ms per application) chosen."""
+    k, kb, t, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(ctx, _load().wh_autotune(ctx, int(applies), ctypes.byref(k), ctypes.byref(kb), ctypes.byref(t),
+                                    ctypes.byref(ms)))
+    return int(k.value), int(kb.value), int(t.value), float(ms.value)
 
 
 def wh_profile_enable(ctx, enable=True):
@@ -355,16 +362,19 @@ class Solver:
     def time_params(self):
         return wh_get_time_params(self.ctx).as_dict()
 
-    def set_tuning(self, kblock=0, tile_x=0, tile_y=0):
-        wh_set_tuning(self.ctx, kblock, tile_x, tile_y)
+    def set_tuning(self, kernel="auto", kblock=0, tile=0):
+        """kernel: "auto", "node", "blocked_2d" or "zcol_3d"."""
+        wh_set_tuning(self.ctx, KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel), kblock, tile)
 
     def tuning(self):
-        return wh_get_tuning(self.ctx)
+        """dict(kernel, kblock, tile, owned=(x, y)) actually used."""
+        k, kb, t, ox, oy = wh_get_tuning(self.ctx)
+        return dict(kernel=KERNEL_NAMES[k], kblock=kb, tile=t, owned=(ox, oy))
 
     def autotune(self, applies=3):
-        """Time every kernel variant on this problem and keep the fastest:
-        returns (steps per pass, tile rows, ms per application)."""
-        return wh_autotune(self.ctx, applies)
+        """Time every kernel variant on this problem and keep the fastest."""
+        k, kb, t, ms = wh_autotune(self.ctx, applies)
+        return dict(kernel=KERNEL_NAMES[k], kblock=kb, tile=t, ms_per_apply=ms)
 
     def apply(self, v, with_forcing=True, out=None):
         out = self.new() if out is None else out

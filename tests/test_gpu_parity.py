@@ -129,8 +129,11 @@ def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods
     _say(f"[blocked] k={kblock} n={n} p={order} c2={c2kind} Np={periods} {prec}")
     grid, c2, f, v = _problem(2, n, order, c2kind, seed=300 + order)
     s = _solver(2, n, order, prec)
-    s.set_tuning(kblock)
-    assert s.tuning()[0] == kblock
+    if kblock == 1:
+        s.set_tuning("node")
+    else:
+        s.set_tuning("blocked_2d", kblock)
+    assert s.tuning()["kblock"] == kblock
     s.set_c2(c2)
     s.set_source(f)
     s.set_frequency(omega, periods=periods)
@@ -154,7 +157,8 @@ def test_blocked_tile_heights(torch, prec, rows, kblock):
     _say(f"[tile rows] {prec} rows={rows} k={kblock}")
     grid, c2, f, v = _problem(2, (173, 211), 4, "var", seed=401)
     s = _solver(2, (173, 211), 4, prec)
-    s.set_tuning(kblock, 0, rows)
+    s.set_tuning("blocked_2d", kblock, rows)
+    assert s.tuning()["tile"] == rows
     s.set_c2(c2)
     s.set_source(f)
     s.set_frequency(37.0)
@@ -162,6 +166,30 @@ def test_blocked_tile_heights(torch, prec, rows, kblock):
     got = s.apply(_to_dev(torch, v), with_forcing=True).cpu().numpy()
     assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
     assert _walls_zero(got)
+
+
+@pytest.mark.parametrize("kernel,tile", [("node", 0), ("zcol_3d", 4), ("zcol_3d", 8), ("zcol_3d", 16)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,order,periods", [((30, 21, 70), 2, 1), ((30, 21, 70), 4, 1), ((3, 4, 5), 4, 2),
+                                             ((70, 9, 33), 2, 1)])
+def test_3d_kernel_variants(torch, kernel, tile, prec, n, order, periods):
+    """3-D: one node per thread and z-column segments of 4, 8, 16 nodes per
+    thread (several segments per column, a tiny grid) against the oracle."""
+    _say(f"[3d variants] {kernel}/{tile} {prec} n={n} p={order}")
+    grid, c2, f, v = _problem(3, n, order, "var", seed=501 + order)
+    s = _solver(3, n, order, prec)
+    s.set_tuning(kernel, 1, tile)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(11.0, periods=periods)
+    tp = oc.time_params(grid, c2, 11.0, periods=periods)
+    vd = _to_dev(torch, v)
+    got = s.apply(vd, with_forcing=True).cpu().numpy()
+    assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
+    assert _walls_zero(got)
+    gotA = s.apply_A(vd).cpu().numpy()
+    assert _err(prec, gotA, oc.apply_A(grid, c2, v, tp), v) <= TOL[prec]
+    assert _walls_zero(gotA)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -172,9 +200,9 @@ def test_autotune_keeps_results(torch, prec):
     s.set_c2(c2)
     s.set_source(f)
     s.set_frequency(44.0)
-    k, rows, ms = s.autotune(2)
-    assert 1 <= k <= 4 and ms > 0
-    assert s.tuning()[0] == k
+    best = s.autotune(2)
+    assert best["ms_per_apply"] > 0
+    assert s.tuning()["kernel"] == best["kernel"] and s.tuning()["kblock"] == best["kblock"]
     tp = oc.time_params(grid, c2, 44.0)
     got = s.apply(_to_dev(torch, v), with_forcing=True).cpu().numpy()
     assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
@@ -208,7 +236,7 @@ def test_wall_values_of_inputs_are_ignored(torch, kblock):
     noisy_f[0, :] = 5.0
     noisy_f[:, -1] = -3.0
     s.set_source(noisy_f)
-    s.set_tuning(kblock)
+    s.set_tuning("node" if kblock == 1 else "blocked_2d", 0 if kblock == 1 else kblock)
     s.set_frequency(14.0)
     noisy_v = v.copy()
     noisy_v[-1, :] = 7.0
@@ -289,7 +317,7 @@ def test_cg_fixed_iteration_count(torch, prec, kblock):
     _say(f"[cg fixed] {prec} k={kblock}")
     grid, c2, f, _ = _problem(2, (44, 37), 4, "var", seed=35)
     s = _solver(2, (44, 37), 4, prec, restart=2)
-    s.set_tuning(kblock)
+    s.set_tuning("node" if kblock == 1 else "blocked_2d", 0 if kblock == 1 else kblock)
     s.set_c2(c2)
     s.set_source(f)
     s.set_frequency(12.0)
