@@ -33,23 +33,19 @@
 namespace wh {
 namespace {
 
-// lane l receives the value of lane l-1 (x - 1); lane 0 receives 0
-__device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
+// lane l receives the value of lane l-1 (x - 1); lane 0 receives 0.  The
+// bound-control form writes 0 for the lane without a source, so no register
+// has to be zeroed first.
+__device__ __forceinline__ int dpp_from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 // lane l receives the value of lane l+1 (x + 1); lane 63 receives 0
-__device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
+__device__ __forceinline__ int dpp_from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
 __device__ __forceinline__ double from_left(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
 }
 __device__ __forceinline__ double from_right(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
 }
 
 // Odd periodic extension of a node index i of an axis with n cells:
@@ -232,18 +228,27 @@ struct RowsPerLane {
   static constexpr int RS = sizeof(T) == 8 ? 8 : 24;
 };
 
+template <typename T, int P, int K, int NW>
+hipError_t launch_if_fits(const StepGeom &g, int ksteps, const void *ip, const void *ic, void *op, void *oc,
+                          double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
+                          const double *v, double *out, hipStream_t s) {
+  constexpr int RS = RowsPerLane<T>::RS;
+  if constexpr (NW * RS - 2 * K * (P / 2) > 0)
+    return launch_typed<T, P, K, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int P, int K>
 hipError_t dispatch_nw(const StepGeom &g, int nw, int ksteps, const void *ip, const void *ic, void *op, void *oc,
                        double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode, const double *v,
                        double *out, hipStream_t s) {
-  constexpr int RS = RowsPerLane<T>::RS;
   switch (nw) {
-    case 4: return launch_typed<T, P, K, RS, 4>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
-    case 8: return launch_typed<T, P, K, RS, 8>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 4: return launch_if_fits<T, P, K, 4>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 8: return launch_if_fits<T, P, K, 8>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     case 16:
       // FP32's 24-row arrays do not fit 1024-thread groups without spilling
       if constexpr (sizeof(T) == 8)
-        return launch_typed<T, P, K, RS, 16>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+        return launch_if_fits<T, P, K, 16>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
