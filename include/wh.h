@@ -237,6 +237,24 @@ WH_API wh_status wh_apply_A(wh_ctx *ctx, const double *v, double *Av);
  * WH_ENONFINITE if a residual became NaN/Inf. */
 WH_API wh_status wh_solve(wh_ctx *ctx, const wh_solve_opts *opts, double *v, wh_solve_info *info);
 
+/* Solve (I - S_h) v = b for a given right-hand side b (device; b may not
+ * alias v) instead of b = W_h(0, f); the source need not be set.  Same
+ * methods, options and results as wh_solve (the FPI iterates v <- S_h v + b). */
+WH_API wh_status wh_solve_rhs(wh_ctx *ctx, const wh_solve_opts *opts, const double *b, double *v,
+                              wh_solve_info *info);
+
+/* Mixed-precision solve by residual correction.  hi: a WH_FP64 context with
+ * c^2, source and frequency set and a workspace sized for restart >= 2; lo: a
+ * context of the same grid, order and time parameters, normally
+ * WH_FP32_STATE.  Each outer iteration forms the FP64 residual
+ * r = b - A_hi v (b = W_h(0, f) in FP64), solves A_lo d = r approximately with
+ * `inner` on lo (its own workspace), and sets v += d, until ||r|| <= outer->rtol
+ * ||b|| or outer->maxit corrections (outer->method is ignored).  info->iters =
+ * corrections, info->applies counts both precisions, info->rel_res is the FP64
+ * residual.  Returns WH_ENOTCONV if outer->rtol was not reached. */
+WH_API wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, const wh_solve_opts *inner,
+                                double *v, wh_solve_info *info);
+
 /* Diagnostic: res = c^2 Delta_{h,p} u + omega^2 u - f on interior nodes,
  * 0 on the walls (device pointers; res may be NULL), and *rel =
  * ||res||_2 / ||f||_2 (host, nullable).  Synchronises the stream. */

@@ -304,7 +304,7 @@ def fpi(grid: Grid, c2, f, tp: dict, iters: int, v0=None, callback=None):
 
 
 def gmres(grid: Grid, c2, f, tp: dict, restart: int = 50, rtol: float = 1e-8, maxit: int = 1000,
-          x0=None, fixed_iters: int | None = None):
+          x0=None, fixed_iters: int | None = None, b=None):
     """Restarted GMRES(m) on (I - S_h) v = b with b = W_h(0, f) (Sec. 5.3).
 
     Textbook Arnoldi with modified Gram-Schmidt and Givens rotations; x0 = 0
@@ -314,7 +314,9 @@ def gmres(grid: Grid, c2, f, tp: dict, restart: int = 50, rtol: float = 1e-8, ma
     the iterate.  Returns (x, info) with info = dict(iters, rel_res, hist).
     """
     mask = interior_mask(grid)
-    b = apply(grid, c2, f, np.zeros(grid.shape), tp, with_forcing=True).ravel()
+    if b is None:
+        b = apply(grid, c2, f, np.zeros(grid.shape), tp, with_forcing=True)
+    b = np.asarray(b, dtype=np.float64).ravel()
     bnorm = float(np.linalg.norm(b))
     x = np.zeros(b.size) if x0 is None else _prep(grid, x0, "x0").ravel().copy()
     x[~mask.ravel()] = 0.0
@@ -377,7 +379,7 @@ def gmres(grid: Grid, c2, f, tp: dict, restart: int = 50, rtol: float = 1e-8, ma
 
 
 def cg(grid: Grid, c2, f, tp: dict, rtol: float = 1e-8, maxit: int = 1000, x0=None,
-       fixed_iters: int | None = None):
+       fixed_iters: int | None = None, b=None):
     """Conjugate gradients on (I - S_h) v = b, b = W_h(0, f), in the inner
     product <u, w> = sum_i u_i w_i / c^2_i.
 
@@ -392,7 +394,9 @@ def cg(grid: Grid, c2, f, tp: dict, rtol: float = 1e-8, maxit: int = 1000, x0=No
     wgt = 1.0 / (np.full(grid.shape, float(c2)) if np.isscalar(c2) else np.asarray(c2, dtype=np.float64))
     ip = lambda a, b: float(np.sum(a * b * wgt))
     A = lambda vec: apply_A(grid, c2, vec, tp)
-    b = apply(grid, c2, f, np.zeros(grid.shape), tp, with_forcing=True)
+    if b is None:
+        b = apply(grid, c2, f, np.zeros(grid.shape), tp, with_forcing=True)
+    b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
     x = np.zeros(grid.shape) if x0 is None else _prep(grid, x0, "x0").copy()
     x[~mask] = 0.0

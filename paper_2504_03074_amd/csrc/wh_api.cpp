@@ -870,7 +870,19 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
 // ---------------------------------------------------------------------------
 // solvers
 // ---------------------------------------------------------------------------
-static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
+// c->b <- the right-hand side: the given device vector, or b = W_h(0, f).
+static wh_status make_rhs(wh_ctx *c, const double *rhs, int *applies) {
+  if (rhs) {
+    WH_HIP(c, hipMemcpyAsync(c->b, rhs, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+    return WH_OK;
+  }
+  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
+  WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));
+  ++*applies;
+  return WH_OK;
+}
+
+static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info, const double *rhs) {
   const int nb = wh::reduction_blocks(c->nodes);
   // ||b||: b = W_h(0, f); when the initial guess is zero the first iterate is b
   double vv;
@@ -879,10 +891,8 @@ static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solv
   if (!std::isfinite(vv)) return fail(c, WH_ENONFINITE, "initial guess is not finite");
   double bnorm = -1.0;
   int applies = 0;
-  if (vv != 0.0) {
-    WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
-    WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));
-    ++applies;
+  if (vv != 0.0 || rhs) {
+    WH_TRY(make_rhs(c, rhs, &applies));
     double bb;
     WH_TRY(dot_dev(c, c->b, c->b, 0));
     WH_TRY(fetch_scalars(c, 0, 1, &bb));
@@ -892,7 +902,12 @@ static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solv
   int k = 0;
   wh_status st = WH_OK;
   for (k = 1; k <= o->maxit; ++k) {
-    WH_TRY(apply_impl(c, v, true, wh::FINAL_FILTER, c->tmp, nullptr));
+    if (rhs) {  // v <- S v + b
+      WH_TRY(apply_impl(c, v, false, wh::FINAL_FILTER, c->tmp, nullptr));
+      WH_HIP(c, wh::launch_add(c->tmp, c->b, c->tmp, c->nodes, c->stream));
+    } else {  // v <- W_h(v, f)
+      WH_TRY(apply_impl(c, v, true, wh::FINAL_FILTER, c->tmp, nullptr));
+    }
     ++applies;
     WH_HIP(c, wh::launch_diff_norm_copy(c->tmp, v, c->nodes, c->partials, nb, c->stream));
     WH_TRY(reduce_to(c, 1, 0));
@@ -929,7 +944,7 @@ static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solv
   return st;
 }
 
-static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info) {
+static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info, const double *rhs) {
   const int m = o->restart;
   if (m < 1 || m > c->ws_restart)
     return fail(c, WH_EINVAL, "restart %d must be in 1..%d (the workspace's restart length)", m, c->ws_restart);
@@ -940,9 +955,7 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
   const int S_H1 = 0, S_H2 = m + 2, S_NRM = 2 * (m + 2);
 
   int applies = 0;
-  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, N, c->stream));
-  WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));  // b = W_h(0, f)
-  ++applies;
+  WH_TRY(make_rhs(c, rhs, &applies));
   double bb;
   WH_TRY(dot_dev(c, c->b, c->b, S_NRM));
   WH_TRY(fetch_scalars(c, S_NRM, 1, &bb));
@@ -1053,7 +1066,7 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
 // Iteration k keeps <r, r>_w and ||r||^2 in device slot (k & 1); the update
 // kernels read their coefficients from device memory, so each iteration
 // synchronises with the host once (for the convergence test).
-static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info) {
+static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve_info *info, const double *rhs) {
   if (c->ws_restart < 2) return fail(c, WH_ENOMEM, "CG needs a workspace sized for restart >= 2");
   const int64_t N = c->nodes;
   const int nb = wh::reduction_blocks(N);
@@ -1064,9 +1077,7 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
   auto slot = [](int64_t k) { return 4 + 2 * (int)(k & 1); };  // [<r,r>_w, <r,r>]
 
   int applies = 0;
-  WH_HIP(c, wh::launch_fill(c->tmp, 0.0, N, c->stream));
-  WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));  // b = W_h(0, f)
-  ++applies;
+  WH_TRY(make_rhs(c, rhs, &applies));
   double bb;
   WH_TRY(dot_dev(c, c->b, c->b, 0));
   WH_TRY(fetch_scalars(c, 0, 1, &bb));
@@ -1142,23 +1153,31 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
   return st;
 }
 
-wh_status wh_solve(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
-  WH_TRY(need(c, true, true, true, true, true));
+static wh_status check_opts(wh_ctx *c, const wh_solve_opts *o) {
   if (!o) return fail(c, WH_EINVAL, "opts is NULL");
   if (o->flags != 0) return fail(c, WH_EINVAL, "opts.flags must be 0");
   if (o->maxit < 1) return fail(c, WH_EINVAL, "maxit must be >= 1");
   if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(c, WH_EINVAL, "rtol must be finite and >= 0");
   if (o->method != WH_SOLVER_FPI && o->method != WH_SOLVER_GMRES && o->method != WH_SOLVER_CG)
     return fail(c, WH_EINVAL, "unknown method");
+  return WH_OK;
+}
+
+static wh_status solve_dispatch(wh_ctx *c, const wh_solve_opts *o, const double *rhs, double *v,
+                                wh_solve_info *info) {
   WH_TRY(set_device(c));
   WH_TRY(check_dev(c, v, "v"));
+  if (rhs) {
+    WH_TRY(check_dev(c, rhs, "b"));
+    if (rhs == v) return fail(c, WH_EINVAL, "b may not alias v");
+  }
   if (info) std::memset(info, 0, sizeof *info);
   const auto t0 = std::chrono::steady_clock::now();
   wh_status st;
   try {
-    if (o->method == WH_SOLVER_FPI) st = solve_fpi(c, o, v, info);
-    else if (o->method == WH_SOLVER_GMRES) st = solve_gmres(c, o, v, info);
-    else st = solve_cg(c, o, v, info);
+    if (o->method == WH_SOLVER_FPI) st = solve_fpi(c, o, v, info, rhs);
+    else if (o->method == WH_SOLVER_GMRES) st = solve_gmres(c, o, v, info, rhs);
+    else st = solve_cg(c, o, v, info, rhs);
   } catch (const std::bad_alloc &) {
     st = fail(c, WH_ENOMEM, "host allocation failed");
   } catch (...) {
@@ -1170,6 +1189,103 @@ wh_status wh_solve(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->mu_pred = predicted_rate(c);
   }
+  return st;
+}
+
+wh_status wh_solve(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info) {
+  WH_TRY(need(c, true, true, true, true, true));
+  WH_TRY(check_opts(c, o));
+  return solve_dispatch(c, o, nullptr, v, info);
+}
+
+wh_status wh_solve_rhs(wh_ctx *c, const wh_solve_opts *o, const double *b, double *v, wh_solve_info *info) {
+  WH_TRY(need(c, true, true, true, false, true));
+  WH_TRY(check_opts(c, o));
+  if (!b) return fail(c, WH_EINVAL, "b is NULL");
+  return solve_dispatch(c, o, b, v, info);
+}
+
+wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, const wh_solve_opts *inner, double *v,
+                         wh_solve_info *info) {
+  WH_TRY(need(hi, true, true, true, true, true));
+  WH_TRY(need(lo, true, true, true, false, true));
+  if (!outer || !inner) return fail(hi, WH_EINVAL, "opts is NULL");
+  if (outer->maxit < 1 || !(outer->rtol > 0.0) || !std::isfinite(outer->rtol))
+    return fail(hi, WH_EINVAL, "outer maxit must be >= 1 and outer rtol finite and > 0");
+  WH_TRY(check_opts(lo, inner));
+  if (hi->prec != WH_FP64) return fail(hi, WH_EINVAL, "the outer context must use WH_FP64");
+  if (hi->device != lo->device) return fail(hi, WH_EINVAL, "contexts on different devices");
+  if (hi->dim != lo->dim || hi->order != lo->order || hi->n[0] != lo->n[0] || hi->n[1] != lo->n[1] ||
+      hi->n[2] != lo->n[2])
+    return fail(hi, WH_EINVAL, "the two contexts must describe the same grid and order");
+  if (hi->tp.nt != lo->tp.nt || hi->tp.periods != lo->tp.periods || hi->tp.dt != lo->tp.dt ||
+      hi->tp.alpha != lo->tp.alpha)
+    return fail(hi, WH_EINVAL, "the two contexts must use the same time parameters");
+  if (hi->ws_restart < 2) return fail(hi, WH_ENOMEM, "the outer context needs a workspace sized for restart >= 2");
+  WH_TRY(set_device(hi));
+  WH_TRY(check_dev(hi, v, "v"));
+  if (info) std::memset(info, 0, sizeof *info);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = hi->nodes;
+  double *r = hi->V, *d = hi->V + hi->ldv;
+  int applies_hi = 0, applies_lo = 0, inner_iters = 0;
+  WH_TRY(make_rhs(hi, nullptr, &applies_hi));
+  double bb;
+  WH_TRY(dot_dev(hi, hi->b, hi->b, 0));
+  WH_TRY(fetch_scalars(hi, 0, 1, &bb));
+  const double bnorm = std::sqrt(bb);
+  if (!std::isfinite(bnorm)) return fail(hi, WH_ENONFINITE, "||b|| is not finite");
+  double rel = 0.0, rel0 = -1.0;
+  int k = 0;
+  wh_status st = WH_OK;
+  for (;;) {
+    // FP64 residual of the current iterate
+    WH_TRY(apply_impl(hi, v, false, wh::FINAL_A, hi->tmp, nullptr));
+    ++applies_hi;
+    WH_HIP(hi, wh::launch_sub(hi->b, hi->tmp, r, N, hi->stream));
+    double rr;
+    WH_TRY(dot_dev(hi, r, r, 0));
+    WH_TRY(fetch_scalars(hi, 0, 1, &rr));
+    rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0;
+    if (!std::isfinite(rel)) {
+      st = fail(hi, WH_ENONFINITE, "mixed-precision residual became non-finite");
+      break;
+    }
+    if (rel0 < 0.0) rel0 = rel;
+    if (outer->on_iter) outer->on_iter(k, rel, outer->user);
+    if (rel <= outer->rtol || k >= outer->maxit) break;
+    // correction from the state-precision operator: A_lo d = r
+    WH_HIP(hi, wh::launch_fill(d, 0.0, N, hi->stream));
+    WH_HIP(hi, hipStreamSynchronize(hi->stream));
+    wh_solve_info in{};
+    const wh_status sl = solve_dispatch(lo, inner, r, d, &in);
+    applies_lo += in.applies;
+    inner_iters += in.iters;
+    if (sl != WH_OK && sl != WH_ENOTCONV) {
+      st = fail(hi, sl, "inner solve failed: %s", lo->err.c_str());
+      break;
+    }
+    WH_HIP(hi, wh::launch_add(v, d, v, N, hi->stream));
+    ++k;
+  }
+  WH_HIP(hi, hipStreamSynchronize(hi->stream));
+  if (info) {
+    info->iters = k;
+    info->applies = applies_hi + applies_lo;
+    info->bnorm = bnorm;
+    info->rel_res = rel;
+    info->scaled_res = rel * bnorm / std::sqrt((double)N);
+    info->cr_last = (k > 0 && rel0 > 0.0) ? std::pow(rel / rel0, 1.0 / k) : NAN;
+    info->cr_avg = info->cr_last;
+    info->ecr = std::pow(info->cr_avg, 1.0 / hi->tp.periods);
+    info->point_steps = applies_hi * point_steps_per_apply(hi) + applies_lo * point_steps_per_apply(lo);
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->mu_pred = predicted_rate(hi);
+  }
+  (void)inner_iters;
+  if (st == WH_OK && rel > outer->rtol)
+    st = fail(hi, WH_ENOTCONV, "mixed-precision refinement reached maxit = %d at relative residual %g",
+              outer->maxit, rel);
   return st;
 }
 

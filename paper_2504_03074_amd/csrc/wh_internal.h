@@ -100,6 +100,8 @@ hipError_t launch_scale_by_rnorm(const double *src, double *dst, const double *n
 // partials of sum (a - b)^2, then b = a
 hipError_t launch_diff_norm_copy(const double *a, double *b, int64_t n, double *partials, int nb,
                                  hipStream_t s);
+// dst = a + b
+hipError_t launch_add(const double *a, const double *b, double *dst, int64_t n, hipStream_t s);
 // dst = a - b
 hipError_t launch_sub(const double *a, const double *b, double *dst, int64_t n, hipStream_t s);
 // partial min/max/non-finite count of src over interior nodes (3 * nb values)

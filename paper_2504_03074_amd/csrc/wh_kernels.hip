@@ -391,6 +391,12 @@ __global__ __launch_bounds__(kRedThreads) void diff_norm_copy_kernel(const doubl
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+__global__ void add_kernel(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ dst,
+                           int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = a[e] + b[e];
+}
+
 __global__ void sub_kernel(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ dst,
                            int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
@@ -642,6 +648,11 @@ hipError_t launch_scale_by_rnorm(const double *src, double *dst, const double *n
 
 hipError_t launch_diff_norm_copy(const double *a, double *b, int64_t n, double *partials, int nb, hipStream_t s) {
   diff_norm_copy_kernel<<<(unsigned)nb, kRedThreads, 0, s>>>(a, b, n, partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const double *a, const double *b, double *dst, int64_t n, hipStream_t s) {
+  add_kernel<<<flat_blocks(n), 256, 0, s>>>(a, b, dst, n);
   return hipGetLastError();
 }
 

@@ -102,6 +102,9 @@ def _load():
         "wh_apply": (st, [_vp, _vp, _vp, ctypes.c_int32]),
         "wh_apply_A": (st, [_vp, _vp, _vp]),
         "wh_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, ctypes.POINTER(wh_solve_info)]),
+        "wh_solve_rhs": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, _vp, ctypes.POINTER(wh_solve_info)]),
+        "wh_solve_mixed": (st, [_vp, _vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(wh_solve_opts), _vp,
+                                ctypes.POINTER(wh_solve_info)]),
         "wh_helmholtz_residual": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "wh_dot": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "wh_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -236,6 +239,38 @@ def wh_solve(ctx, opts: wh_solve_opts, v: int) -> tuple[int, wh_solve_info]:
     if st not in (WH_OK, WH_ENOTCONV):
         _check(ctx, st)
     return st, info
+
+
+def wh_solve_rhs(ctx, opts: wh_solve_opts, b: int, v: int) -> tuple[int, wh_solve_info]:
+    info = wh_solve_info()
+    st = _load().wh_solve_rhs(ctx, ctypes.byref(opts), _vp(b), _vp(v), ctypes.byref(info))
+    if st not in (WH_OK, WH_ENOTCONV):
+        _check(ctx, st)
+    return st, info
+
+
+def wh_solve_mixed(hi, lo, outer: wh_solve_opts, inner: wh_solve_opts, v: int) -> tuple[int, wh_solve_info]:
+    info = wh_solve_info()
+    st = _load().wh_solve_mixed(hi, lo, ctypes.byref(outer), ctypes.byref(inner), _vp(v), ctypes.byref(info))
+    if st not in (WH_OK, WH_ENOTCONV):
+        _check(hi, st)
+    return st, info
+
+
+def make_opts(method="cg", rtol=1e-8, maxit=1000, restart=2, callback=None):
+    """wh_solve_opts (and the ctypes callback object that must outlive the call)."""
+    opts = wh_solve_opts()
+    opts.method = {"gmres": WH_SOLVER_GMRES, "fpi": WH_SOLVER_FPI, "cg": WH_SOLVER_CG}[method]
+    opts.restart = int(restart)
+    opts.maxit = int(maxit)
+    opts.flags = 0
+    opts.rtol = float(rtol)
+    cb = None
+    if callback is not None:
+        cb = WH_ITER_CALLBACK(lambda k, r, u: callback(k, r))
+        opts.on_iter = cb
+    opts.user = None
+    return opts, cb
 
 
 def wh_helmholtz_residual(ctx, u: int, res: int | None) -> float:
@@ -393,20 +428,26 @@ class Solver:
                        fil.data_ptr() if fil is not None else None)
         return fin, fil
 
-    def solve(self, method="gmres", rtol=1e-8, maxit=1000, restart=None, v0=None, callback=None):
+    def solve(self, method="gmres", rtol=1e-8, maxit=1000, restart=None, v0=None, callback=None, b=None):
+        """Solve (I - S_h) v = b, b = W_h(0, f) unless given (device tensor)."""
         v = self.new() if v0 is None else v0.clone()
-        opts = wh_solve_opts()
-        opts.method = {"gmres": WH_SOLVER_GMRES, "fpi": WH_SOLVER_FPI, "cg": WH_SOLVER_CG}[method]
-        opts.restart = int(self.restart if restart is None else restart)
-        opts.maxit = int(maxit)
-        opts.flags = 0
-        opts.rtol = float(rtol)
-        cb = None
-        if callback is not None:
-            cb = WH_ITER_CALLBACK(lambda k, r, u: callback(k, r))
-            opts.on_iter = cb
-        opts.user = None
-        st, info = wh_solve(self.ctx, opts, self._dev(v, "v"))
+        opts, cb = make_opts(method, rtol, maxit, self.restart if restart is None else restart, callback)
+        if b is None:
+            st, info = wh_solve(self.ctx, opts, self._dev(v, "v"))
+        else:
+            st, info = wh_solve_rhs(self.ctx, opts, self._dev(b, "b"), self._dev(v, "v"))
+        d = info.as_dict()
+        d["converged"] = st == WH_OK
+        return v, d
+
+    def solve_mixed(self, lo, rtol=1e-8, maxit=50, inner_method="cg", inner_rtol=1e-3, inner_maxit=2000,
+                    v0=None, callback=None):
+        """Residual correction: FP64 residuals on this solver, corrections
+        from `lo` (a Solver of the same problem, normally precision="fp32")."""
+        v = self.new() if v0 is None else v0.clone()
+        outer, cb = make_opts("cg", rtol, maxit, 2, callback)
+        inner, _ = make_opts(inner_method, inner_rtol, inner_maxit, max(lo.restart, 2))
+        st, info = wh_solve_mixed(self.ctx, lo.ctx, outer, inner, self._dev(v, "v"))
         d = info.as_dict()
         d["converged"] = st == WH_OK
         return v, d

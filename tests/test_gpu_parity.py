@@ -385,6 +385,47 @@ def test_cg_converges_to_direct_solve(torch, dim, n, order):
     assert _rel(x.cpu().numpy(), U) <= 1e-9
 
 
+@pytest.mark.parametrize("method", ["cg", "gmres", "fpi"])
+def test_solve_with_given_rhs(torch, method):
+    """(I - S_h) x = b for a given b: the solution satisfies the oracle's A x = b."""
+    _say(f"[solve rhs] {method}")
+    grid, c2, _, b = _problem(2, (28, 23), 4, "var", seed=81)
+    omega = _best_omega(grid, c2, np.linspace(5.0, 15.0, 21))
+    s = _solver(2, (28, 23), 4, "fp64", restart=30)
+    s.set_c2(c2)
+    s.set_frequency(omega)
+    tp = oc.time_params(grid, c2, omega)
+    x, info = s.solve(method=method, rtol=1e-12, maxit=20000, restart=30, b=_to_dev(torch, b))
+    assert info["converged"], info
+    xn = x.cpu().numpy()
+    assert _rel(oc.apply_A(grid, c2, xn, tp), b) <= 1e-11
+    want, _ = oc.cg(grid, c2, None, tp, rtol=1e-13, maxit=20000, b=b)
+    assert _rel(xn, want) <= 1e-9
+
+
+@pytest.mark.parametrize("inner", ["cg", "gmres"])
+def test_mixed_precision_refinement(torch, inner):
+    """FP64 residual correction around FP32-state inner solves reaches the FP64
+    discrete Helmholtz solution; the plain FP32-state solve does not."""
+    _say(f"[mixed] inner={inner}")
+    grid, c2, f, _ = _problem(2, (40, 31), 4, "var", seed=91)
+    omega = _best_omega(grid, c2, np.linspace(5.0, 15.0, 21))
+    hi = _solver(2, (40, 31), 4, "fp64", restart=2)
+    lo = _solver(2, (40, 31), 4, "fp32", restart=30)
+    for s in (hi, lo):
+        s.set_c2(c2)
+        s.set_source(f)
+        s.set_frequency(omega)
+    x, info = hi.solve_mixed(lo, rtol=1e-11, maxit=40, inner_method=inner, inner_rtol=1e-4)
+    assert info["converged"], info
+    U = cf.dhs_direct(grid, c2, f, omega)
+    err_mixed = _rel(x.cpu().numpy(), U)
+    assert err_mixed <= 1e-9
+    x32, _ = lo.solve(method="cg", rtol=1e-6, maxit=5000)
+    err_32 = _rel(x32.cpu().numpy(), U)
+    assert err_32 > 10 * err_mixed
+
+
 def test_fpi_with_tolerance_reaches_closed_form(torch):
     _say("[fpi rtol]")
     grid = oc.Grid(2, (24, 24), 2)
