@@ -329,6 +329,51 @@ WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
 /* Synchronise the stream and return the counters accumulated so far. */
 WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent 2-D problems advanced together.  Each problem is
+ * a fully configured context (grid, workspace sized for restart >= 2, c^2,
+ * source, frequency; same order and precision across the batch; different
+ * grid sizes and frequencies allowed).  Every blocked pass of all problems
+ * still stepping is one kernel launch, the first steps of all problems are one
+ * launch, and the batched CG iteration is captured once in a HIP graph and
+ * replayed.  The batch uses the problems' workspaces and its own stream; the
+ * contexts must outlive it and must not be used concurrently with it.
+ * ---------------------------------------------------------------------- */
+typedef struct wh_batch wh_batch;
+
+#define WH_MAX_BATCH 1024
+
+WH_API wh_status wh_batch_create(wh_batch **out, int32_t device, void *stream);
+WH_API void wh_batch_destroy(wh_batch *batch);
+WH_API const char *wh_batch_last_error(const wh_batch *batch);
+
+/* Append a problem; *index (nullable) receives its position. */
+WH_API wh_status wh_batch_add(wh_batch *batch, wh_ctx *ctx, int32_t *index);
+
+/* Steps per launch and tile rows of the batched blocked kernel (0 = default;
+ * same values as WH_KERNEL_BLOCKED_2D up to FP64 64 / FP32 192 rows).  Before
+ * wh_batch_finalize. */
+WH_API wh_status wh_batch_set_tuning(wh_batch *batch, int32_t kblock, int32_t tile);
+
+/* Bytes of device workspace for the batch's tables (after adding problems). */
+WH_API wh_status wh_batch_workspace_size(wh_batch *batch, size_t *bytes);
+
+/* Bind the table workspace (256-byte aligned, caller-owned) and freeze the
+ * batch (no more wh_batch_add). */
+WH_API wh_status wh_batch_finalize(wh_batch *batch, void *workspace, size_t bytes);
+
+/* out[i] = W_h(v[i], s f_i) for every problem i (host arrays of device
+ * pointers, in wh_batch_add order; out[i] may not alias v[i]).  Enqueued on
+ * the batch's stream. */
+WH_API wh_status wh_batch_apply(wh_batch *batch, const double *const *v, double *const *out, int32_t with_forcing);
+
+/* Solve every problem's (I - S_h) x_i = b_i, b_i = W_h(0, f_i), by CG in the
+ * 1/c^2 inner product (opts->method must be WH_SOLVER_CG; rtol > 0) until
+ * each reaches rtol or maxit iterations.  x[i] (device) holds the guess on
+ * entry and the iterate on exit; info (nullable) is an array with one entry
+ * per problem (rel_res is the true residual at exit).  Synchronises. */
+WH_API wh_status wh_batch_solve(wh_batch *batch, const wh_solve_opts *opts, double *const *x, wh_solve_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,9 +5,9 @@ The compute path is the C ABI in ``include/wh.h`` (``libwh.so``); ``wh``
 is its Python binding and ``Solver`` a convenience object over torch tensors.
 """
 from .wh import (  # noqa: F401
-    Solver, WhError, library, wh_compute_time_params, wh_version,
+    Batch, Solver, WhError, library, wh_compute_time_params, wh_version,
     WH_FP64, WH_FP32_STATE, WH_SOLVER_FPI, WH_SOLVER_GMRES, WH_SOLVER_CG,
 )
 
-__all__ = ["Solver", "WhError", "library", "wh_compute_time_params", "wh_version",
+__all__ = ["Batch", "Solver", "WhError", "library", "wh_compute_time_params", "wh_version",
            "WH_FP64", "WH_FP32_STATE", "WH_SOLVER_FPI", "WH_SOLVER_GMRES", "WH_SOLVER_CG"]

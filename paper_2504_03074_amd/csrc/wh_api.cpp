@@ -1290,3 +1290,564 @@ wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, con
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent 2-D problems
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kBatchStride = 8;  // device scalars per table row
+// scalar slots of a row: 0 <p,q>_w; 2,3 / 4,5 <r,r>_w, <r,r> of even / odd
+// iterations
+inline int cg_slot(int64_t k) { return 2 + 2 * (int)(k & 1); }
+}  // namespace
+
+struct wh_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;  // caller's stream (apply)
+  hipStream_t own = nullptr;     // private stream: solve, graph capture
+  hipEvent_t ev = nullptr;
+  std::string err;
+  std::vector<wh_ctx *> probs;  // insertion order
+  bool finalized = false;
+  int prec = WH_FP64, order = 2, K = 0, rows = 0;  // 0 = default
+  std::vector<int> coef_off;  // per problem
+  std::vector<int> passes;    // per problem
+  // tables of the current selection (host mirror)
+  std::vector<int> ids;
+  std::vector<wh::BatchDesc> desc;
+  std::vector<wh::BatchFirst> first;
+  std::vector<wh::BatchVec> vecs;
+  std::vector<int> prefix, active_at;
+  int maxpasses = 0, first_blocks = 0, red_blocks = 0;
+  // device tables, carved from the bound workspace
+  wh::BatchDesc *d_desc = nullptr;
+  wh::BatchFirst *d_first = nullptr;
+  wh::BlockCoef *d_coef = nullptr;
+  int *d_prefix = nullptr;
+  wh::BatchVec *d_vecs = nullptr, *d_vecs_e = nullptr;
+  double *d_part = nullptr, *d_sc = nullptr;
+  double *pinned = nullptr;  // WH_MAX_BATCH rows of scalars
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+wh_status bfail(wh_batch *b, wh_status st, const char *fmt, ...) {
+  if (b) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+  }
+  return st;
+}
+
+#define WH_BHIP(b, call)                                                                                 \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess) return bfail((b), WH_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_resolve_tuning(wh_batch *b) {
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  if (b->K == 0) b->K = fp32 ? 3 : 4;
+  if (b->rows == 0) b->rows = wh::block_default_rows(fp32);
+}
+
+int batch_passes(const wh_ctx *c, int K) {
+  const int64_t steps = (int64_t)c->tp.nt * c->tp.periods - 1;
+  return (int)((steps + K - 1) / K);
+}
+
+struct BatchLayout {
+  size_t desc, first, coef, prefix, vecs, vecs_e, part, sc, total;
+};
+
+BatchLayout batch_layout(size_t P, size_t ncoef, int red_blocks) {
+  BatchLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.desc = take(P * sizeof(wh::BatchDesc));
+  L.first = take(P * sizeof(wh::BatchFirst));
+  L.coef = take(ncoef * sizeof(wh::BlockCoef));
+  L.prefix = take((P + 1) * sizeof(int));
+  L.vecs = take(P * sizeof(wh::BatchVec));
+  L.vecs_e = take(P * sizeof(wh::BatchVec));
+  L.part = take((size_t)2 * red_blocks * 8);
+  L.sc = take(P * kBatchStride * 8);
+  L.total = off;
+  return L;
+}
+
+// Build and upload the tables of the problems `ids` (any order; stored by
+// decreasing pass count).  The apply of problem i reads in[i] and writes
+// out[i]; its Krylov vectors are x[i] (nullable) and the r, p, q columns of
+// its workspace.  Row scalars are uploaded from `rowsc` (P x kBatchStride,
+// by problem) when given.
+wh_status batch_select(wh_batch *b, std::vector<int> ids, const double *const *in, double *const *out, bool forcing,
+                       double *const *x, const double *rowsc, hipStream_t s) {
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  std::stable_sort(ids.begin(), ids.end(), [&](int a, int c) { return b->passes[a] > b->passes[c]; });
+  int ox, oy;
+  wh::block_tile_shape(fp32, b->order, b->K, b->rows, &ox, &oy);
+  const size_t n = ids.size();
+  b->ids = ids;
+  b->desc.assign(n, wh::BatchDesc{});
+  b->first.assign(n, wh::BatchFirst{});
+  b->vecs.assign(n, wh::BatchVec{});
+  b->prefix.assign(n + 1, 0);
+  b->first_blocks = 0;
+  b->red_blocks = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const int i = ids[t];
+    wh_ctx *c = b->probs[(size_t)i];
+    const double dt2 = c->tp.dt * c->tp.dt;
+    const void *c2 = c->c2_is_const ? nullptr : c->c2;
+    wh::BatchDesc &d = b->desc[t];
+    d.g = geometry(c, dt2);
+    d.c2 = c2;
+    d.f = forcing ? c->f : nullptr;
+    for (int q = 0; q < 4; ++q) d.W[q] = c->W[q];
+    d.acc = c->acc;
+    d.v = in[i];
+    d.out = out[i];
+    d.tiles_x = (int)((c->n[0] + 1 + ox - 1) / ox);
+    d.tiles = d.tiles_x * (int)((c->n[1] + 1 + oy - 1) / oy);
+    d.steps = (int)((int64_t)c->tp.nt * c->tp.periods - 1);
+    d.passes = b->passes[(size_t)i];
+    d.coef_offset = b->coef_off[(size_t)i];
+    b->prefix[t + 1] = b->prefix[t] + d.tiles;
+    wh::BatchFirst &f = b->first[t];
+    f.half = geometry(c, 0.5 * dt2);
+    f.v = in[i];
+    f.W0 = c->W[0];
+    f.W1 = c->W[1];
+    f.acc = c->acc;
+    f.c2 = c2;
+    f.f = forcing ? c->f : nullptr;
+    f.g0 = forcing ? -0.5 * dt2 : 0.0;
+    f.w0 = c->wts[0];
+    f.w1 = c->wts[1];
+    f.block_offset = b->first_blocks;
+    b->first_blocks += wh::batch_node_blocks(c->nodes);
+    wh::BatchVec &v = b->vecs[t];
+    v.x = x ? x[i] : nullptr;
+    v.r = c->V;
+    v.p = c->V + c->ldv;
+    v.q = c->V + 2 * c->ldv;
+    v.b = c->b;
+    v.c2 = c2;
+    v.n = c->nodes;
+    v.block_offset = b->red_blocks;
+    v.nblocks = wh::batch_red_blocks(c->nodes);
+    v.active = 1;
+    b->red_blocks += v.nblocks;
+  }
+  b->maxpasses = n ? b->desc[0].passes : 0;
+  b->active_at.assign((size_t)b->maxpasses, 0);
+  for (int j = 0; j < b->maxpasses; ++j)
+    for (size_t t = 0; t < n; ++t)
+      if (b->desc[t].passes > j) b->active_at[(size_t)j] = (int)t + 1;
+  std::vector<wh::BatchVec> ve = b->vecs;
+  for (auto &v : ve) v.c2 = nullptr;  // Euclidean products
+  WH_BHIP(b, hipStreamSynchronize(s));  // host staging below is reused
+  WH_BHIP(b, hipMemcpyAsync(b->d_desc, b->desc.data(), n * sizeof(wh::BatchDesc), hipMemcpyHostToDevice, s));
+  WH_BHIP(b, hipMemcpyAsync(b->d_first, b->first.data(), n * sizeof(wh::BatchFirst), hipMemcpyHostToDevice, s));
+  WH_BHIP(b, hipMemcpyAsync(b->d_prefix, b->prefix.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  WH_BHIP(b, hipMemcpyAsync(b->d_vecs, b->vecs.data(), n * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
+  WH_BHIP(b, hipMemcpyAsync(b->d_vecs_e, ve.data(), n * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
+  if (rowsc) {
+    for (size_t t = 0; t < n; ++t)
+      std::memcpy(b->pinned + t * kBatchStride, rowsc + (size_t)ids[t] * kBatchStride, kBatchStride * 8);
+    WH_BHIP(b, hipMemcpyAsync(b->d_sc, b->pinned, n * kBatchStride * 8, hipMemcpyHostToDevice, s));
+  }
+  WH_BHIP(b, hipStreamSynchronize(s));
+  return WH_OK;
+}
+
+// Launches of one batched application over the selected problems.
+wh_status batch_enqueue_apply(wh_batch *b, bool forcing, int final_mode, hipStream_t s) {
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  const int n = (int)b->ids.size();
+  if (n == 0) return WH_OK;
+  WH_BHIP(b, wh::launch_batch_first_step(fp32, b->order, b->d_first, n, b->first_blocks, s));
+  for (int j = 0; j < b->maxpasses; ++j) {
+    const int na = b->active_at[(size_t)j];
+    WH_BHIP(b, wh::launch_batch_block_steps(fp32, b->order, b->K, b->rows, forcing, b->d_desc, b->d_prefix, na,
+                                            b->prefix[(size_t)na], j, b->d_coef, final_mode, s));
+  }
+  return WH_OK;
+}
+
+// Copy the selected rows' scalars to rowsc (by problem).
+wh_status batch_fetch(wh_batch *b, double *rowsc, hipStream_t s) {
+  const size_t n = b->ids.size();
+  WH_BHIP(b, hipMemcpyAsync(b->pinned, b->d_sc, n * kBatchStride * 8, hipMemcpyDeviceToHost, s));
+  WH_BHIP(b, hipStreamSynchronize(s));
+  for (size_t t = 0; t < n; ++t)
+    std::memcpy(rowsc + (size_t)b->ids[t] * kBatchStride, b->pinned + t * kBatchStride, kBatchStride * 8);
+  return WH_OK;
+}
+
+void batch_drop_graphs(wh_batch *b) {
+  for (int i = 0; i < 2; ++i) {
+    if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+    if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    b->exec[i] = nullptr;
+    b->graph[i] = nullptr;
+  }
+}
+
+// Capture one CG iteration over the selected problems for each slot parity:
+// q = A p, <p,q>_w, x += a p, r -= a q (with the new <r,r>_w, <r,r>), and
+// p = r + beta p.
+wh_status batch_capture(wh_batch *b) {
+  batch_drop_graphs(b);
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  const int n = (int)b->ids.size();
+  for (int par = 0; par < 2; ++par) {
+    const int cur = cg_slot(par), nxt = cg_slot(par + 1);
+    WH_BHIP(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+    wh_status st = batch_enqueue_apply(b, false, wh::FINAL_A, b->own);
+    if (st == WH_OK) {
+      hipError_t e = wh::launch_batch_dot(fp32, b->d_vecs, n, b->red_blocks, 0, b->d_part, b->d_sc, kBatchStride,
+                                          b->own);
+      if (e == hipSuccess)
+        e = wh::launch_batch_cg_update(fp32, b->d_vecs, n, b->red_blocks, b->d_sc + cur, b->d_sc, kBatchStride,
+                                       b->d_part, b->d_sc + nxt, b->own);
+      if (e == hipSuccess)
+        e = wh::launch_batch_xpay(b->d_vecs, n, b->red_blocks, b->d_sc + nxt, b->d_sc + cur, kBatchStride, b->own);
+      if (e != hipSuccess) st = bfail(b, WH_EDEVICE, "batched CG launch failed: %s", hipGetErrorString(e));
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->own, &g);
+    if (st != WH_OK || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (st != WH_OK) return st;
+      return bfail(b, WH_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    }
+    b->graph[par] = g;
+    WH_BHIP(b, hipGraphInstantiate(&b->exec[par], g, nullptr, nullptr, 0));
+  }
+  return WH_OK;
+}
+
+wh_status batch_need(wh_batch *b) {
+  if (!b) return WH_EINVAL;
+  if (!b->finalized) return bfail(b, WH_ESTATE, "batch not finalized (call wh_batch_finalize)");
+  return WH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wh_status wh_batch_create(wh_batch **out, int32_t device, void *stream) {
+  if (!out) return WH_EINVAL;
+  *out = nullptr;
+  wh_batch *b = new (std::nothrow) wh_batch();
+  if (!b) return WH_ENOMEM;
+  b->device = device;
+  b->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void **)&b->pinned, (size_t)WH_MAX_BATCH * kBatchStride * 8, hipHostMallocDefault) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->own) (void)hipStreamDestroy(b->own);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    delete b;
+    return WH_EDEVICE;
+  }
+  *out = b;
+  return WH_OK;
+}
+
+void wh_batch_destroy(wh_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->own);
+  batch_drop_graphs(b);
+  (void)hipEventDestroy(b->ev);
+  (void)hipStreamDestroy(b->own);
+  (void)hipHostFree(b->pinned);
+  delete b;
+}
+
+const char *wh_batch_last_error(const wh_batch *b) { return b ? b->err.c_str() : "no batch"; }
+
+wh_status wh_batch_add(wh_batch *b, wh_ctx *c, int32_t *index) {
+  if (!b || !c) return WH_EINVAL;
+  if (b->finalized) return bfail(b, WH_ESTATE, "batch already finalized");
+  if ((int)b->probs.size() >= WH_MAX_BATCH) return bfail(b, WH_EINVAL, "at most %d problems per batch", WH_MAX_BATCH);
+  if (!c->grid_set || !c->ws || !c->c2_set || !c->f_set || !c->freq_set)
+    return bfail(b, WH_ESTATE, "problem must have grid, workspace, c^2, source and frequency set");
+  if (c->dim != 2) return bfail(b, WH_EINVAL, "batches hold 2-D problems");
+  if (c->ws_restart < 2) return bfail(b, WH_ENOMEM, "problem workspace must be sized for restart >= 2");
+  if (c->device != b->device) return bfail(b, WH_EINVAL, "problem on another device");
+  for (wh_ctx *o : b->probs)
+    if (o == c) return bfail(b, WH_EINVAL, "problem added twice");
+  if (!b->probs.empty() && (c->order != b->order || c->prec != b->prec))
+    return bfail(b, WH_EINVAL, "all problems of a batch share order and precision");
+  b->order = c->order;
+  b->prec = c->prec;
+  b->probs.push_back(c);
+  if (index) *index = (int32_t)b->probs.size() - 1;
+  return WH_OK;
+}
+
+wh_status wh_batch_set_tuning(wh_batch *b, int32_t kblock, int32_t tile) {
+  if (!b) return WH_EINVAL;
+  if (b->finalized) return bfail(b, WH_ESTATE, "batch already finalized");
+  if (b->probs.empty()) return bfail(b, WH_ESTATE, "add problems first");
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  const int K = kblock == 0 ? (fp32 ? 3 : 4) : kblock;
+  const int rows = tile == 0 ? wh::block_default_rows(fp32) : tile;
+  if (K < 2 || !wh::block_config_supported(fp32, b->order, K, rows) || rows > 8 * (fp32 ? 24 : 8))
+    return bfail(b, WH_EINVAL, "kblock %d / tile %d not supported for batches", kblock, tile);
+  b->K = K;
+  b->rows = rows;
+  return WH_OK;
+}
+
+wh_status wh_batch_workspace_size(wh_batch *b, size_t *bytes) {
+  if (!b || !bytes) return WH_EINVAL;
+  if (b->probs.empty()) return bfail(b, WH_ESTATE, "add problems first");
+  batch_resolve_tuning(b);
+  size_t ncoef = 0;
+  int red = 0;
+  for (wh_ctx *c : b->probs) {
+    ncoef += (size_t)batch_passes(c, b->K);
+    red += wh::batch_red_blocks(c->nodes);
+  }
+  *bytes = batch_layout(b->probs.size(), ncoef, red).total;
+  return WH_OK;
+}
+
+wh_status wh_batch_finalize(wh_batch *b, void *workspace, size_t bytes) {
+  if (!b) return WH_EINVAL;
+  if (b->finalized) return bfail(b, WH_ESTATE, "batch already finalized");
+  size_t need_bytes = 0;
+  WH_TRY(wh_batch_workspace_size(b, &need_bytes));
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return bfail(b, WH_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  if (bytes < need_bytes) return bfail(b, WH_ENOMEM, "batch workspace too small: %zu given, %zu needed", bytes, need_bytes);
+  WH_BHIP(b, hipSetDevice(b->device));
+  if (!is_device_ptr(workspace)) return bfail(b, WH_EINVAL, "workspace is not device memory");
+  const size_t P = b->probs.size();
+  // per (problem, pass) step coefficients: steps 1 + j K + q, weights of the
+  // levels they produce
+  std::vector<wh::BlockCoef> coefs;
+  b->coef_off.assign(P, 0);
+  b->passes.assign(P, 0);
+  int red = 0;
+  for (size_t i = 0; i < P; ++i) {
+    wh_ctx *c = b->probs[i];
+    b->passes[i] = batch_passes(c, b->K);
+    b->coef_off[i] = (int)coefs.size();
+    for (int j = 0; j < b->passes[i]; ++j) {
+      wh::BlockCoef cf{};
+      for (int q = 0; q < b->K; ++q) {
+        const int64_t n = 1 + (int64_t)j * b->K + q;
+        if (n + 1 >= (int64_t)c->wts.size()) break;
+        cf.gn[q] = c->frc[(size_t)n];
+        cf.wn[q] = c->wts[(size_t)n + 1];
+      }
+      coefs.push_back(cf);
+    }
+    red += wh::batch_red_blocks(c->nodes);
+  }
+  const BatchLayout L = batch_layout(P, coefs.size(), red);
+  char *base = static_cast<char *>(workspace);
+  b->d_desc = reinterpret_cast<wh::BatchDesc *>(base + L.desc);
+  b->d_first = reinterpret_cast<wh::BatchFirst *>(base + L.first);
+  b->d_coef = reinterpret_cast<wh::BlockCoef *>(base + L.coef);
+  b->d_prefix = reinterpret_cast<int *>(base + L.prefix);
+  b->d_vecs = reinterpret_cast<wh::BatchVec *>(base + L.vecs);
+  b->d_vecs_e = reinterpret_cast<wh::BatchVec *>(base + L.vecs_e);
+  b->d_part = reinterpret_cast<double *>(base + L.part);
+  b->d_sc = reinterpret_cast<double *>(base + L.sc);
+  WH_BHIP(b, hipMemcpyAsync(b->d_coef, coefs.data(), coefs.size() * sizeof(wh::BlockCoef), hipMemcpyHostToDevice,
+                            b->own));
+  WH_BHIP(b, hipStreamSynchronize(b->own));
+  b->finalized = true;
+  return WH_OK;
+}
+
+wh_status wh_batch_apply(wh_batch *b, const double *const *v, double *const *out, int32_t with_forcing) {
+  WH_TRY(batch_need(b));
+  if (!v || !out) return bfail(b, WH_EINVAL, "pointer arrays are NULL");
+  const size_t P = b->probs.size();
+  for (size_t i = 0; i < P; ++i)
+    if (!v[i] || !out[i] || !is_device_ptr(v[i]) || !is_device_ptr(out[i]) || v[i] == out[i])
+      return bfail(b, WH_EINVAL, "problem %zu: input and output must be distinct device arrays", i);
+  WH_BHIP(b, hipSetDevice(b->device));
+  std::vector<int> all(P);
+  for (size_t i = 0; i < P; ++i) all[i] = (int)i;
+  WH_TRY(batch_select(b, all, v, out, with_forcing != 0, nullptr, nullptr, b->stream));
+  return batch_enqueue_apply(b, with_forcing != 0, wh::FINAL_FILTER, b->stream);
+}
+
+wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, wh_solve_info *info) {
+  WH_TRY(batch_need(b));
+  if (!o || !x) return bfail(b, WH_EINVAL, "opts or x is NULL");
+  if (o->method != WH_SOLVER_CG) return bfail(b, WH_EINVAL, "batches are solved with WH_SOLVER_CG");
+  if (o->flags != 0) return bfail(b, WH_EINVAL, "opts.flags must be 0");
+  if (o->maxit < 1 || !(o->rtol > 0.0) || !std::isfinite(o->rtol))
+    return bfail(b, WH_EINVAL, "maxit must be >= 1 and rtol finite and > 0");
+  WH_BHIP(b, hipSetDevice(b->device));
+  const size_t P = b->probs.size();
+  for (size_t i = 0; i < P; ++i)
+    if (!x[i] || !is_device_ptr(x[i])) return bfail(b, WH_EINVAL, "x[%zu] is not device memory", i);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = b->own;
+  // order after the caller's stream and the problems' own uploads
+  for (wh_ctx *c : b->probs) WH_BHIP(b, hipStreamSynchronize(c->stream));
+  WH_BHIP(b, hipEventRecord(b->ev, b->stream));
+  WH_BHIP(b, hipStreamWaitEvent(s, b->ev, 0));
+
+  std::vector<const double *> zero(P), xin(P), pin(P);
+  std::vector<double *> bout(P), qout(P);
+  for (size_t i = 0; i < P; ++i) {
+    wh_ctx *c = b->probs[i];
+    WH_BHIP(b, wh::launch_fill(c->tmp, 0.0, c->nodes, s));
+    zero[i] = c->tmp;
+    bout[i] = c->b;
+    xin[i] = x[i];
+    pin[i] = c->V + c->ldv;
+    qout[i] = c->V + 2 * c->ldv;
+  }
+  std::vector<double> sc(P * kBatchStride, 0.0), bnorm(P, 0.0), rel(P, 1.0);
+  std::vector<int> iters(P, 0), applies(P, 0);
+  std::vector<char> done(P, 0);
+  std::vector<int> all(P);
+  for (size_t i = 0; i < P; ++i) all[i] = (int)i;
+  const bool fp32 = b->prec == WH_FP32_STATE;
+
+  // b_i = W_h(0, f_i) and ||b_i||: r = b - 0, then <r,r>
+  WH_TRY(batch_select(b, all, zero.data(), bout.data(), true, x, nullptr, s));
+  WH_TRY(batch_enqueue_apply(b, true, wh::FINAL_FILTER, s));
+  for (auto &a : applies) ++a;
+  {
+    // Euclidean table with q = 0
+    std::vector<wh::BatchVec> ve = b->vecs;
+    for (size_t t = 0; t < P; ++t) {
+      ve[t].c2 = nullptr;
+      ve[t].q = b->probs[(size_t)b->ids[t]]->tmp;
+    }
+    WH_BHIP(b, hipMemcpyAsync(b->d_vecs_e, ve.data(), P * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
+    WH_BHIP(b, wh::launch_batch_residual(b->d_vecs_e, (int)P, b->red_blocks, s));
+    WH_BHIP(b, wh::launch_batch_dot(false, b->d_vecs_e, (int)P, b->red_blocks, 1, b->d_part, b->d_sc + 1,
+                                    kBatchStride, s));
+    WH_TRY(batch_fetch(b, sc.data(), s));  // synchronises: ve may go
+  }
+  for (size_t i = 0; i < P; ++i) {
+    bnorm[i] = std::sqrt(sc[i * kBatchStride + 1]);
+    if (!std::isfinite(bnorm[i])) return bfail(b, WH_ENONFINITE, "problem %zu: ||b|| is not finite", i);
+  }
+
+  // r = b - A x, p = r and the slot(k) scalars, for the problems `ids`
+  auto restart = [&](const std::vector<int> &ids, int64_t k) -> wh_status {
+    WH_TRY(batch_select(b, ids, xin.data(), qout.data(), false, x, nullptr, s));
+    WH_TRY(batch_enqueue_apply(b, false, wh::FINAL_A, s));
+    const int n = (int)ids.size();
+    WH_BHIP(b, wh::launch_batch_residual(b->d_vecs, n, b->red_blocks, s));
+    WH_BHIP(b, wh::launch_batch_dot(fp32, b->d_vecs, n, b->red_blocks, 1, b->d_part, b->d_sc + cg_slot(k),
+                                    kBatchStride, s));
+    WH_BHIP(b, wh::launch_batch_dot(false, b->d_vecs_e, n, b->red_blocks, 1, b->d_part, b->d_sc + cg_slot(k) + 1,
+                                    kBatchStride, s));
+    WH_TRY(batch_fetch(b, sc.data(), s));
+    for (int i : ids) {
+      ++applies[(size_t)i];
+      const double ee = sc[(size_t)i * kBatchStride + cg_slot(k) + 1];
+      rel[(size_t)i] = bnorm[(size_t)i] > 0.0 ? std::sqrt(ee) / bnorm[(size_t)i] : 0.0;
+    }
+    return WH_OK;
+  };
+
+  wh_status st = WH_OK;
+  int64_t k = 0;
+  WH_TRY(restart(all, k));
+  std::vector<int> active;
+  for (int i : all)
+    if (bnorm[(size_t)i] > 0.0 && rel[(size_t)i] > o->rtol) active.push_back(i);
+    else done[(size_t)i] = 1;
+  bool reselect = true;
+  while (!active.empty() && k < o->maxit) {
+    if (reselect) {
+      WH_TRY(batch_select(b, active, pin.data(), qout.data(), false, x, sc.data(), s));
+      WH_TRY(batch_capture(b));
+      reselect = false;
+    }
+    WH_BHIP(b, hipGraphLaunch(b->exec[k & 1], s));
+    ++k;
+    WH_TRY(batch_fetch(b, sc.data(), s));
+    std::vector<int> hit, keep;
+    for (int i : active) {
+      const double *row = sc.data() + (size_t)i * kBatchStride;
+      ++applies[(size_t)i];
+      iters[(size_t)i] = (int)k;
+      const double pq = row[0], ee = row[cg_slot(k) + 1];
+      if (!std::isfinite(pq) || !std::isfinite(ee)) {
+        st = bfail(b, WH_ENONFINITE, "problem %d became non-finite at iteration %lld", i, (long long)k);
+        break;
+      }
+      if (!(pq > 0.0)) {
+        st = bfail(b, WH_ENOTCONV, "problem %d: CG breakdown, <p, A p> = %g at iteration %lld", i, pq, (long long)k);
+        break;
+      }
+      rel[(size_t)i] = std::sqrt(ee) / bnorm[(size_t)i];
+      (rel[(size_t)i] <= o->rtol ? hit : keep).push_back(i);
+    }
+    if (st != WH_OK) break;
+    if (o->on_iter) {
+      double worst = 0.0;
+      for (int i : active) worst = std::max(worst, rel[(size_t)i]);
+      o->on_iter((int32_t)k, worst, o->user);
+    }
+    if (!hit.empty()) {
+      // confirm with the true residual; problems that drifted continue from it
+      WH_TRY(restart(hit, k));
+      for (int i : hit)
+        if (rel[(size_t)i] <= o->rtol) done[(size_t)i] = 1;
+        else keep.push_back(i);
+      active = keep;
+      reselect = true;
+    }
+  }
+  // problems stopped by maxit report their true residual
+  if (st == WH_OK && !active.empty()) WH_TRY(restart(active, k));
+  WH_BHIP(b, hipStreamSynchronize(s));
+  batch_drop_graphs(b);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int unconverged = 0;
+  for (size_t i = 0; i < P; ++i) {
+    unconverged += rel[i] > o->rtol;
+    if (!info) continue;
+    wh_ctx *c = b->probs[i];
+    wh_solve_info &in = info[i];
+    std::memset(&in, 0, sizeof in);
+    in.iters = iters[i];
+    in.applies = applies[i];
+    in.rel_res = rel[i];
+    in.bnorm = bnorm[i];
+    in.scaled_res = rel[i] * bnorm[i] / std::sqrt((double)c->nodes);
+    in.cr_last = in.cr_avg = in.ecr = NAN;
+    in.mu_pred = NAN;
+    in.seconds = secs;
+    in.point_steps = applies[i] * point_steps_per_apply(c);
+  }
+  if (st == WH_OK && unconverged)
+    st = bfail(b, WH_ENOTCONV, "%d problems did not reach rtol within maxit = %d", unconverged, o->maxit);
+  return st;
+}
+
+}  // extern "C"

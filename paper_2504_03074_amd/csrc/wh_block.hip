@@ -59,11 +59,21 @@ __device__ __forceinline__ int reflect(int i, int n, float &sign) {
   return two_n - m;
 }
 
+// XCD-aware tile order: consecutive work-groups are dispatched round-robin
+// over the 8 XCDs; give each XCD a contiguous run of tiles so that the halo
+// re-reads of neighbouring tiles hit the same L2.
+__device__ __forceinline__ int xcd_tile_order(int b, int nblk) {
+  const int per_xcd = (nblk + 7) / 8;
+  return (b % 8) * per_xcd + (b / 8);
+}
+
+// K (ksteps <= K) leapfrog steps of one tile (tx, ty) of one grid: the body
+// shared by the single-grid and the batched kernels.
 template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
-__global__ __launch_bounds__(64 * NW) void block_steps_kernel(
-    StepGeom g, int ksteps, int tiles_x, int tiles_total, const T *__restrict__ in_prev,
-    const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
-    const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
+__device__ __forceinline__ void advance_tile(
+    const StepGeom &g, int ksteps, int tx, int ty, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
+    T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
+    const T *__restrict__ fg, const BlockCoef &coef, int mode, const double *__restrict__ v,
     double *__restrict__ out) {
   constexpr int R = P / 2;
   constexpr int H = K * R;
@@ -71,16 +81,6 @@ __global__ __launch_bounds__(64 * NW) void block_steps_kernel(
   constexpr int OY = NW * RS - 2 * H;
   static_assert(OX > 0 && OY > 0, "tile too small for the halo");
   static_assert(RS >= R, "each wave must hold at least r rows");
-
-  // XCD-aware tile order: consecutive work-groups are dispatched round-robin
-  // over the 8 XCDs; give each XCD a contiguous run of tiles so that the halo
-  // re-reads of neighbouring tiles hit the same L2.
-  const int nblk = gridDim.x;
-  const int b = blockIdx.x;
-  const int per_xcd = (nblk + 7) / 8;
-  const int tile = (b % 8) * per_xcd + (b / 8);
-  if (tile >= tiles_total) return;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -184,6 +184,54 @@ __global__ __launch_bounds__(64 * NW) void block_steps_kernel(
     else if (mode == FINAL_FILTER) out[id] = ACC[q];
     else out[id] = v[id] - ACC[q];
   }
+}
+
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
+__global__ __launch_bounds__(64 * NW) void block_steps_kernel(
+    StepGeom g, int ksteps, int tiles_x, int tiles_total, const T *__restrict__ in_prev,
+    const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
+    const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
+    double *__restrict__ out) {
+  const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
+  if (tile >= tiles_total) return;
+  advance_tile<T, P, K, RS, NW, FORCE, CVAR>(g, ksteps, tile % tiles_x, tile / tiles_x, in_prev, in_cur, out_prev,
+                                             out_cur, acc, c2g, fg, coef, mode, v, out);
+}
+
+// Batched pass: work-group -> (problem, tile) through the prefix sums of the
+// active problems' tile counts (problems are sorted by pass count, so the
+// problems still stepping in pass `pass` are a prefix of the table).
+template <typename T, int P, int K, int RS, int NW, bool FORCE>
+__global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchDesc *__restrict__ descs,
+                                                                    const int *__restrict__ tile_prefix, int nactive,
+                                                                    int pass, const BlockCoef *__restrict__ coefs,
+                                                                    int final_mode) {
+  const int total = tile_prefix[nactive];
+  const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
+  if (tile >= total) return;
+  int lo = 0, hi = nactive - 1;  // last problem whose first tile is <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_prefix[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchDesc &d = descs[lo];
+  const int local = tile - tile_prefix[lo];
+  const int ks = min(K, d.steps - pass * K);
+  const int mode = (pass == d.passes - 1) ? final_mode : ACCUMULATE;
+  const bool even = (pass & 1) == 0;
+  const T *ip = static_cast<const T *>(even ? d.W[0] : d.W[2]);
+  const T *ic = static_cast<const T *>(even ? d.W[1] : d.W[3]);
+  T *op = static_cast<T *>(even ? d.W[2] : d.W[0]);
+  T *oc = static_cast<T *>(even ? d.W[3] : d.W[1]);
+  const BlockCoef coef = coefs[d.coef_offset + pass];
+  const int tx = local % d.tiles_x, ty = local / d.tiles_x;
+  if (d.c2)
+    advance_tile<T, P, K, RS, NW, FORCE, true>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, static_cast<const T *>(d.c2),
+                                               static_cast<const T *>(d.f), coef, mode, d.v, d.out);
+  else
+    advance_tile<T, P, K, RS, NW, FORCE, false>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, nullptr,
+                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out);
 }
 
 template <typename T, int P, int K, int RS, int NW>
@@ -299,6 +347,60 @@ hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, 
   if (g.order == 2)
     return dispatch_k<double, 2>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
   return dispatch_k<double, 4>(g, K, nw, ksteps, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
+}
+
+namespace {
+template <typename T, int P, int K, int NW>
+hipError_t batch_launch_fits(bool force, const BatchDesc *descs, const int *tile_prefix, int nactive, int total,
+                             int pass, const BlockCoef *coefs, int final_mode, hipStream_t s) {
+  constexpr int RS = RowsPerLane<T>::RS;
+  if constexpr (NW * RS - 2 * K * (P / 2) > 0) {
+    const int blocks = ((total + 7) / 8) * 8;
+    if (force)
+      batch_block_steps_kernel<T, P, K, RS, NW, true><<<blocks, 64 * NW, 0, s>>>(descs, tile_prefix, nactive, pass,
+                                                                                 coefs, final_mode);
+    else
+      batch_block_steps_kernel<T, P, K, RS, NW, false><<<blocks, 64 * NW, 0, s>>>(descs, tile_prefix, nactive, pass,
+                                                                                  coefs, final_mode);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P, int K>
+hipError_t batch_nw(int nw, bool force, const BatchDesc *descs, const int *tp, int nactive, int total, int pass,
+                    const BlockCoef *coefs, int final_mode, hipStream_t s) {
+  switch (nw) {
+    case 4: return batch_launch_fits<T, P, K, 4>(force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    case 8: return batch_launch_fits<T, P, K, 8>(force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int P>
+hipError_t batch_k(int K, int nw, bool force, const BatchDesc *descs, const int *tp, int nactive, int total, int pass,
+                   const BlockCoef *coefs, int final_mode, hipStream_t s) {
+  switch (K) {
+    case 2: return batch_nw<T, P, 2>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    case 3: return batch_nw<T, P, 3>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    case 4: return batch_nw<T, P, 4>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_batch_block_steps(bool fp32, int order, int K, int rows, bool force, const BatchDesc *descs,
+                                    const int *tile_prefix, int nactive, int total_tiles, int pass,
+                                    const BlockCoef *coefs, int final_mode, hipStream_t s) {
+  if (total_tiles <= 0) return hipSuccess;
+  if (!block_config_supported(fp32, order, K, rows)) return hipErrorInvalidValue;
+  const int nw = rows / (fp32 ? RowsPerLane<float>::RS : RowsPerLane<double>::RS);
+  if (fp32) {
+    if (order == 2) return batch_k<float, 2>(K, nw, force, descs, tile_prefix, nactive, total_tiles, pass, coefs, final_mode, s);
+    return batch_k<float, 4>(K, nw, force, descs, tile_prefix, nactive, total_tiles, pass, coefs, final_mode, s);
+  }
+  if (order == 2) return batch_k<double, 2>(K, nw, force, descs, tile_prefix, nactive, total_tiles, pass, coefs, final_mode, s);
+  return batch_k<double, 4>(K, nw, force, descs, tile_prefix, nactive, total_tiles, pass, coefs, final_mode, s);
 }
 
 }  // namespace wh

@@ -67,6 +67,68 @@ hipError_t launch_step3d_zcol(bool fp32, const StepGeom &g, int zb, const void *
                               double *out, hipStream_t s);
 bool zcol_supported(int zb);
 
+// ---------------------------------------------------------------------------
+// Batches of independent 2-D problems (same order and precision).
+// ---------------------------------------------------------------------------
+// One problem of a batched blocked pass (device-resident table).
+struct BatchDesc {
+  StepGeom g;           // stencil scaled by dt^2
+  const void *c2;       // null: constant g.c2const
+  const void *f;        // null: no forcing
+  void *W[4];           // state buffers: pass j reads pair j%2, writes the other
+  double *acc;          // FP64 filter accumulator
+  const double *v;      // input of the application (read by FINAL_A)
+  double *out;          // output of the application
+  int tiles_x, tiles;   // tile grid of this problem for the batch's (K, rows)
+  int steps;            // leapfrog steps after the first (N - 1)
+  int passes;           // ceil(steps / K)
+  int coef_offset;      // index of this problem's first BlockCoef
+};
+// Pass `pass` of every active problem (the first nactive of the table, sorted
+// by pass count) in one launch; tile_prefix[i] = first tile of problem i.
+hipError_t launch_batch_block_steps(bool fp32, int order, int K, int rows, bool force, const BatchDesc *descs,
+                                    const int *tile_prefix, int nactive, int total_tiles, int pass,
+                                    const BlockCoef *coefs, int final_mode, hipStream_t s);
+
+// First step of every problem of a batch in one launch.
+struct BatchFirst {
+  StepGeom half;        // stencil scaled by dt^2 / 2
+  const double *v;
+  void *W0, *W1;
+  double *acc;
+  const void *c2;       // null: constant
+  const void *f;        // null: no forcing
+  double g0, w0, w1;
+  int block_offset;     // first thread block of this problem
+};
+hipError_t launch_batch_first_step(bool fp32, int order, const BatchFirst *firsts, int nprob, int total_blocks,
+                                   hipStream_t s);
+int batch_node_blocks(int64_t nodes);
+
+// Vectors of one problem for the batched Krylov kernels.
+struct BatchVec {
+  double *x, *r, *p, *q;
+  const double *b;
+  const void *c2;       // weights 1/c2 of the inner product (null: 1)
+  int64_t n;
+  int block_offset;     // first reduction block of this problem
+  int nblocks;
+  int active;           // 0: frozen (converged)
+};
+int batch_red_blocks(int64_t n);
+// out[2*i] = <a_i, b_i>_w (which = 0: a = p, b = q; which = 1: a = b = r)
+hipError_t launch_batch_dot(bool fp32_c2, const BatchVec *vecs, int nprob, int total_blocks, int which,
+                            double *partials, double *out, int out_stride, hipStream_t s);
+// x += a p, r -= a q with a = num[i*stride]/den[i*stride]; then
+// out[2*i] = <r,r>_w, out[2*i+1] = <r,r>.  Frozen problems are untouched.
+hipError_t launch_batch_cg_update(bool fp32_c2, const BatchVec *vecs, int nprob, int total_blocks, const double *num,
+                                  const double *den, int stride, double *partials, double *out, hipStream_t s);
+// p = r + (num/den) p for active problems
+hipError_t launch_batch_xpay(const BatchVec *vecs, int nprob, int total_blocks, const double *num, const double *den,
+                             int stride, hipStream_t s);
+// r = b - q, p = r for every problem (start or restart of CG)
+hipError_t launch_batch_residual(const BatchVec *vecs, int nprob, int total_blocks, hipStream_t s);
+
 // Convert/copy helpers.
 hipError_t launch_to_state(bool fp32, const double *src, void *dst, int64_t n, hipStream_t s);
 hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n, hipStream_t s);

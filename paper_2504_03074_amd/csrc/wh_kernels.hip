@@ -112,15 +112,13 @@ __device__ __forceinline__ Coef<T> coef_of(const StepGeom &g) {
   return Coef<T>{static_cast<T>(g.kx), static_cast<T>(g.ky), static_cast<T>(g.kz), static_cast<T>(g.kc)};
 }
 
+// First step at node (i, j, k): W0 = v (0 on walls), W1 = W0 + c2 (half-scaled
+// stencil of v) + g0 f, acc = w0 W0 + w1 W1.
 template <typename T, int DIM, int P>
-__global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
-    StepGeom g, const double *__restrict__ v, T *__restrict__ W0, T *__restrict__ W1,
-    double *__restrict__ acc, const T *__restrict__ c2, const T *__restrict__ f, double g0, double w0,
-    double w1) {
-  const int i = blockIdx.x * kBlockX + threadIdx.x;
-  const int j = blockIdx.y * kBlockY + threadIdx.y;
-  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
-  if (i > g.nx || j > g.ny) return;
+__device__ __forceinline__ void first_step_node(const StepGeom &g, int i, int j, int k, const double *__restrict__ v,
+                                                T *__restrict__ W0, T *__restrict__ W1, double *__restrict__ acc,
+                                                const T *__restrict__ c2, const T *__restrict__ f, double g0,
+                                                double w0, double w1) {
   const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
   const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
   if (wall) {
@@ -137,6 +135,37 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
   W0[idx] = u0;
   W1[idx] = u1;
   acc[idx] = w0 * static_cast<double>(u0) + w1 * static_cast<double>(u1);
+}
+
+template <typename T, int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
+    StepGeom g, const double *__restrict__ v, T *__restrict__ W0, T *__restrict__ W1,
+    double *__restrict__ acc, const T *__restrict__ c2, const T *__restrict__ f, double g0, double w0,
+    double w1) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  first_step_node<T, DIM, P>(g, i, j, k, v, W0, W1, acc, c2, f, g0, w0, w1);
+}
+
+// Batched first step of 2-D problems: flat node blocks, problem found from
+// the block offsets (ascending).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void batch_first_step_kernel(const BatchFirst *__restrict__ firsts, int nprob) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (firsts[mid].block_offset <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchFirst &d = firsts[lo];
+  const int64_t e = (int64_t)(b - d.block_offset) * 256 + threadIdx.x;
+  if (e >= d.half.nodes) return;
+  const int i = (int)(e % d.half.sy), j = (int)(e / d.half.sy);
+  first_step_node<T, 2, P>(d.half, i, j, 0, d.v, static_cast<T *>(d.W0), static_cast<T *>(d.W1), d.acc,
+                           static_cast<const T *>(d.c2), static_cast<const T *>(d.f), d.g0, d.w0, d.w1);
 }
 
 template <typename T, int DIM, int P>
@@ -460,6 +489,103 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void helmholtz_residual_kernel(
   res[idx] = c2v * lap + omega2 * u[idx] - fv;
 }
 
+// ---------------------------------------------------------------------------
+// batched Krylov vector kernels (problem found from the block offsets)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_problem(const BatchVec *__restrict__ vecs, int nprob, int b) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (vecs[mid].block_offset <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename TC>
+__device__ __forceinline__ double inv_weight(const void *c2, int64_t e) {
+  return c2 ? 1.0 / static_cast<double>(static_cast<const TC *>(c2)[e]) : 1.0;
+}
+
+template <typename TC>
+__global__ __launch_bounds__(kRedThreads) void batch_dot_kernel(const BatchVec *__restrict__ vecs, int nprob,
+                                                                int which, double *__restrict__ partials) {
+  __shared__ double sm[4];
+  const int i = batch_problem(vecs, nprob, blockIdx.x);
+  const BatchVec &d = vecs[i];
+  const int lb = blockIdx.x - d.block_offset;
+  const double *a = which == 0 ? d.p : d.r;
+  const double *c = which == 0 ? d.q : d.r;
+  double s = 0.0;
+  for (int64_t e = (int64_t)lb * kRedThreads + threadIdx.x; e < d.n; e += (int64_t)d.nblocks * kRedThreads)
+    s += a[e] * c[e] * inv_weight<TC>(d.c2, e);
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// out[i * stride + row] = sum of the problem's partials of that row
+__global__ __launch_bounds__(kRedThreads) void batch_reduce_kernel(const BatchVec *__restrict__ vecs,
+                                                                   const double *__restrict__ partials, int rows,
+                                                                   double *__restrict__ out, int stride) {
+  __shared__ double sm[4];
+  const BatchVec &d = vecs[blockIdx.x];
+  for (int row = 0; row < rows; ++row) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < d.nblocks; b += kRedThreads) s += partials[(int64_t)(d.block_offset + b) * rows + row];
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride + row] = s;
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(kRedThreads) void batch_cg_update_kernel(const BatchVec *__restrict__ vecs, int nprob,
+                                                                      const double *__restrict__ num,
+                                                                      const double *__restrict__ den, int stride,
+                                                                      double *__restrict__ partials) {
+  __shared__ double sm[4];
+  const int i = batch_problem(vecs, nprob, blockIdx.x);
+  const BatchVec &d = vecs[i];
+  const int lb = blockIdx.x - d.block_offset;
+  double sw = 0.0, se = 0.0;
+  if (d.active) {
+    const double a = num[(int64_t)i * stride] / den[(int64_t)i * stride];
+    for (int64_t e = (int64_t)lb * kRedThreads + threadIdx.x; e < d.n; e += (int64_t)d.nblocks * kRedThreads) {
+      d.x[e] += a * d.p[e];
+      const double re = d.r[e] - a * d.q[e];
+      d.r[e] = re;
+      se += re * re;
+      sw += re * re * inv_weight<TC>(d.c2, e);
+    }
+  }
+  sw = block_sum(sw, sm);
+  if (threadIdx.x == 0) partials[2 * (int64_t)blockIdx.x] = sw;
+  se = block_sum(se, sm);
+  if (threadIdx.x == 0) partials[2 * (int64_t)blockIdx.x + 1] = se;
+}
+
+__global__ __launch_bounds__(kRedThreads) void batch_xpay_kernel(const BatchVec *__restrict__ vecs, int nprob,
+                                                                 const double *__restrict__ num,
+                                                                 const double *__restrict__ den, int stride) {
+  const int i = batch_problem(vecs, nprob, blockIdx.x);
+  const BatchVec &d = vecs[i];
+  if (!d.active) return;
+  const int lb = blockIdx.x - d.block_offset;
+  const double bt = num[(int64_t)i * stride] / den[(int64_t)i * stride];
+  for (int64_t e = (int64_t)lb * kRedThreads + threadIdx.x; e < d.n; e += (int64_t)d.nblocks * kRedThreads)
+    d.p[e] = d.r[e] + bt * d.p[e];
+}
+
+__global__ __launch_bounds__(kRedThreads) void batch_residual_kernel(const BatchVec *__restrict__ vecs, int nprob) {
+  const int i = batch_problem(vecs, nprob, blockIdx.x);
+  const BatchVec &d = vecs[i];
+  const int lb = blockIdx.x - d.block_offset;
+  for (int64_t e = (int64_t)lb * kRedThreads + threadIdx.x; e < d.n; e += (int64_t)d.nblocks * kRedThreads) {
+    const double re = d.b[e] - d.q[e];
+    d.r[e] = re;
+    d.p[e] = re;
+  }
+}
+
 dim3 node_grid(const StepGeom &g) {
   return dim3((unsigned)((g.nx + 1 + kBlockX - 1) / kBlockX), (unsigned)((g.ny + 1 + kBlockY - 1) / kBlockY),
               (unsigned)(g.dim == 3 ? g.nz + 1 : 1));
@@ -687,6 +813,57 @@ hipError_t launch_helmholtz_residual(const StepGeom &g, const double *u, const v
   else if (fp32_c2) residual_typed<float, double>(g, u, c2, f, omega2, res, s);
   else if (fp32_f) residual_typed<double, float>(g, u, c2, f, omega2, res, s);
   else residual_typed<double, double>(g, u, c2, f, omega2, res, s);
+  return hipGetLastError();
+}
+
+int batch_node_blocks(int64_t nodes) { return (int)((nodes + 255) / 256); }
+
+hipError_t launch_batch_first_step(bool fp32, int order, const BatchFirst *firsts, int nprob, int total_blocks,
+                                   hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  if (fp32) {
+    if (order == 2) batch_first_step_kernel<float, 2><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+    else batch_first_step_kernel<float, 4><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+  } else {
+    if (order == 2) batch_first_step_kernel<double, 2><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+    else batch_first_step_kernel<double, 4><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+  }
+  return hipGetLastError();
+}
+
+int batch_red_blocks(int64_t n) {
+  int64_t b = (n + 8 * kRedThreads - 1) / (8 * kRedThreads);
+  if (b > 512) b = 512;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_batch_dot(bool fp32_c2, const BatchVec *vecs, int nprob, int total_blocks, int which,
+                            double *partials, double *out, int out_stride, hipStream_t s) {
+  if (fp32_c2) batch_dot_kernel<float><<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob, which, partials);
+  else batch_dot_kernel<double><<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob, which, partials);
+  batch_reduce_kernel<<<nprob, kRedThreads, 0, s>>>(vecs, partials, 1, out, out_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cg_update(bool fp32_c2, const BatchVec *vecs, int nprob, int total_blocks, const double *num,
+                                  const double *den, int stride, double *partials, double *out, hipStream_t s) {
+  if (fp32_c2)
+    batch_cg_update_kernel<float><<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob, num, den, stride, partials);
+  else
+    batch_cg_update_kernel<double><<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob, num, den, stride, partials);
+  batch_reduce_kernel<<<nprob, kRedThreads, 0, s>>>(vecs, partials, 2, out, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_xpay(const BatchVec *vecs, int nprob, int total_blocks, const double *num, const double *den,
+                             int stride, hipStream_t s) {
+  batch_xpay_kernel<<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob, num, den, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_residual(const BatchVec *vecs, int nprob, int total_blocks, hipStream_t s) {
+  batch_residual_kernel<<<total_blocks, kRedThreads, 0, s>>>(vecs, nprob);
   return hipGetLastError();
 }
 

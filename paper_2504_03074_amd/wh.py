@@ -115,6 +115,16 @@ def _load():
         "wh_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
         "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
+        "wh_batch_create": (st, [ctypes.POINTER(_vp), ctypes.c_int32, _vp]),
+        "wh_batch_destroy": (None, [_vp]),
+        "wh_batch_last_error": (ctypes.c_char_p, [_vp]),
+        "wh_batch_add": (st, [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]),
+        "wh_batch_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "wh_batch_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "wh_batch_finalize": (st, [_vp, _vp, ctypes.c_size_t]),
+        "wh_batch_apply": (st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32]),
+        "wh_batch_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(_vp),
+                                ctypes.POINTER(wh_solve_info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -313,9 +323,70 @@ def wh_profile_read(ctx) -> wh_profile:
     _check(ctx, _load().wh_profile_read(ctx, ctypes.byref(out)))
     return out
 
+def _bcheck(batch, status):
+    if status != WH_OK:
+        msg = _load().wh_batch_last_error(batch).decode() if batch else ""
+        raise WhError(status, msg)
+
+
+def _ptrs(ptrs):
+    arr = (_vp * max(len(ptrs), 1))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def wh_batch_create(device: int = 0, stream: int | None = None):
+    b = _vp()
+    st = _load().wh_batch_create(ctypes.byref(b), int(device), _vp(stream) if stream else None)
+    if st != WH_OK:
+        raise WhError(st, f"wh_batch_create(device={device}) failed")
+    return b
+
+
+def wh_batch_destroy(batch):
+    _load().wh_batch_destroy(batch)
+
+
+def wh_batch_last_error(batch) -> str:
+    return _load().wh_batch_last_error(batch).decode()
+
+
+def wh_batch_add(batch, ctx) -> int:
+    idx = ctypes.c_int32()
+    _bcheck(batch, _load().wh_batch_add(batch, ctx, ctypes.byref(idx)))
+    return idx.value
+
+
+def wh_batch_set_tuning(batch, kblock=0, tile=0):
+    _bcheck(batch, _load().wh_batch_set_tuning(batch, int(kblock), int(tile)))
+
+
+def wh_batch_workspace_size(batch) -> int:
+    out = ctypes.c_size_t()
+    _bcheck(batch, _load().wh_batch_workspace_size(batch, ctypes.byref(out)))
+    return out.value
+
+
+def wh_batch_finalize(batch, ptr: int, nbytes: int):
+    _bcheck(batch, _load().wh_batch_finalize(batch, _vp(ptr), nbytes))
+
+
+def wh_batch_apply(batch, v: list, out: list, with_forcing: bool):
+    _bcheck(batch, _load().wh_batch_apply(batch, _ptrs(v), _ptrs(out), int(bool(with_forcing))))
+
+
+def wh_batch_solve(batch, opts: wh_solve_opts, x: list) -> tuple[int, list]:
+    """Returns (status, [wh_solve_info per problem]); WH_ENOTCONV is returned."""
+    infos = (wh_solve_info * max(len(x), 1))()
+    st = _load().wh_batch_solve(batch, ctypes.byref(opts), _ptrs(x), infos)
+    if st not in (WH_OK, WH_ENOTCONV):
+        _bcheck(batch, st)
+    return st, [infos[i] for i in range(len(x))]
+
 
 # --------------------------------------------------------------------------
-# convenience object over torch tensors
+# convenience objects over torch tensors
 # --------------------------------------------------------------------------
 class Solver:
     """One WaveHoltz problem on one GPU, with torch-owned device memory.
@@ -465,3 +536,54 @@ class Solver:
 
     def profile_read(self):
         return wh_profile_read(self.ctx).as_dict()
+
+
+class Batch:
+    """Independent 2-D problems (configured Solvers with restart >= 2, same
+    order and precision) advanced together: one launch per blocked pass of
+    all problems, the CG iteration captured in a HIP graph."""
+
+    def __init__(self, solvers, kblock=0, tile=0, device=0, stream=None):
+        import torch
+        self._torch = torch
+        self.solvers = list(solvers)
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.batch = wh_batch_create(device, self.stream.cuda_stream)
+        for s in self.solvers:
+            wh_batch_add(self.batch, s.ctx)
+        if kblock or tile:
+            wh_batch_set_tuning(self.batch, kblock, tile)
+        nbytes = wh_batch_workspace_size(self.batch)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        wh_batch_finalize(self.batch, self.workspace.data_ptr(), nbytes)
+
+    def __len__(self):
+        return len(self.solvers)
+
+    def __del__(self):
+        b = getattr(self, "batch", None)
+        if b:
+            try:
+                wh_batch_destroy(b)
+            except Exception:
+                pass
+            self.batch = None
+
+    def apply(self, vs, with_forcing=True, outs=None):
+        outs = [s.new() for s in self.solvers] if outs is None else outs
+        wh_batch_apply(self.batch, [s._dev(v, "v") for s, v in zip(self.solvers, vs)],
+                       [s._dev(o, "out") for s, o in zip(self.solvers, outs)], with_forcing)
+        return outs
+
+    def solve(self, rtol=1e-8, maxit=1000, x0=None, callback=None):
+        """CG on every problem; returns (list of x, list of info dicts)."""
+        xs = [s.new() for s in self.solvers] if x0 is None else [x.clone() for x in x0]
+        opts, cb = make_opts("cg", rtol, maxit, 2, callback)
+        st, infos = wh_batch_solve(self.batch, opts, [s._dev(x, "x") for s, x in zip(self.solvers, xs)])
+        out = []
+        for inf in infos:
+            d = inf.as_dict()
+            d["converged"] = d["rel_res"] <= rtol
+            out.append(d)
+        return xs, out
