@@ -23,6 +23,9 @@ CPU oracle's rate on a bounded sample of the same workload.
 Other modes (used to produce the committed rocprofv3 summaries):
   --mode kernel   only W_h applications (A v) of the workload, no solver
   --mode copy     a plain device copy of known size (HBM counter calibration)
+  --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
+                  omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
+                  by the batched CG, against solving them one at a time
 """
 import argparse
 import json
@@ -53,7 +56,10 @@ def parse():
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch"], default="solve")
+    ap.add_argument("--count", type=int, default=64, help="problems in --mode batch")
+    ap.add_argument("--no-sequential", dest="sequential", action="store_false", default=True,
+                    help="--mode batch: skip the one-at-a-time comparison")
     ap.add_argument("--applies", type=int, default=20, help="applications timed in --mode kernel")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
@@ -107,6 +113,124 @@ def cpu_baseline(w, order, nt_sample):
     return pts / sec / 1e9, oc.max_threads(), sec, tp["nt"]
 
 
+def run_batch(args, dev):
+    """Many independent solves at once: the batched CG (one launch per blocked
+    pass over all problems, the iteration replayed from a HIP graph) against
+    the same solves one at a time through the single-problem path."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Batch, Solver
+
+    probs = wl.batched_problems(args.count)
+    solvers = []
+    for p in probs:
+        s = Solver(2, (p["n"], p["n"]), order=p["order"], precision=args.precision, restart=2)
+        s.set_c2(p["c2"])
+        s.set_source(wl.materialise_source(2, p["n"], p["source"]))
+        s.set_frequency(p["omega"], periods=p["periods"], cfl_frac=p["cfl"])
+        solvers.append(s)
+    batch = Batch(solvers, kblock=args.kblock, tile=args.tile)
+    if args.autotune:
+        log(f"batch autotune: {batch.autotune(3)}")
+    tun = batch.tuning()
+    nts = [s.time_params["nt"] for s in solvers]
+    pts_apply = [(p["n"] - 1) ** 2 * nt for p, nt in zip(probs, nts)]
+    log(f"{len(probs)} problems, nt {min(nts)}..{max(nts)}, sizes "
+        + ", ".join(f"{n}^2 x{sum(p['n'] == n for p in probs)}" for n in (256, 512, 1024)))
+
+    # batched apply: algorithmic bytes over event-timed duration
+    zeros = [s.new() for s in solvers]
+    outs = [s.new() for s in solvers]
+    batch.apply(zeros, with_forcing=False, outs=outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(args.applies // 4, 3)
+    e0.record()
+    for _ in range(reps):
+        batch.apply(zeros, with_forcing=False, outs=outs)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / reps
+    T = 8 if args.precision == "fp64" else 4
+    kb = tun["kblock"]
+    alg_bytes = 0.0
+    for p, nt in zip(probs, nts):
+        interior = (p["n"] - 1) ** 2
+        passes = math.ceil((nt * p["periods"] - 1) / kb)
+        # first step: v read, W^0, W^1 and the accumulator written; each
+        # pass: two levels read and written, accumulator read and written
+        alg_bytes += interior * ((8 + 2 * T + 8) + passes * (4 * T + 16))
+    achieved = alg_bytes / (apply_ms * 1e-3) / 1e9
+
+    def progress(k, rel):
+        if k % 500 == 0:
+            log(f"  iteration {k}: worst residual estimate {rel:.3e}")
+
+    for i in range(args.warmup):
+        log(f"warmup batched solve {i + 1}/{args.warmup}")
+        batch.solve(rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        xs, infos = batch.solve(rtol=args.rtol, maxit=args.maxit, callback=progress)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    pts = sum(i["applies"] * pa for i, pa in zip(infos, pts_apply))
+    value = pts / elapsed / 1e9
+    its = [i["iters"] for i in infos]
+    helm = max(s.helmholtz_residual(x) for s, x in zip(solvers, xs))
+    log(f"batched: {elapsed:.2f}s, {value:.1f} GPts/s, iterations {min(its)}..{max(its)}")
+
+    seq = None
+    if args.sequential:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        spts = 0
+        for s, pa in zip(solvers, pts_apply):
+            x, inf = s.solve(method="cg", rtol=args.rtol, maxit=args.maxit)
+            spts += inf["applies"] * pa
+        torch.cuda.synchronize()
+        st = time.perf_counter() - t0
+        seq = {"time_to_residual_s": round(st, 4), "GPts_per_s": round(spts / st / 1e9, 3)}
+        log(f"one at a time: {st:.2f}s, {spts / st / 1e9:.1f} GPts/s")
+
+    result = {
+        "metric": "grid-pt updates/s (GPts/s, % HBM roofline) + time to Helmholtz residual 1e-8",
+        "value": round(value, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-state/f64-acc",
+        "data": "synthetic (seeded frequencies, sizes and Gaussian sources)",
+        "config": {
+            "workload": f"{len(probs)} batched 2-D solves, grids {{256,512,1024}}^2, omega ~ U[20,150], c = 1, "
+                        f"2nd order, one Gaussian source each, batched CG to {args.rtol:g}",
+            "problems": len(probs), "rtol": args.rtol, "precision": args.precision,
+            "steps_per_launch": kb, "tile_rows": tun["tile"], "autotuned": bool(args.autotune),
+        },
+        "time_to_residual_s": round(elapsed, 4),
+        "converged": all(i["converged"] for i in infos),
+        "max_rel_res": max(i["rel_res"] for i in infos),
+        "helmholtz_rel_res_max": helm,
+        "iters_min_median_max": [min(its), int(np.median(its)), max(its)],
+        "sequential": seq,
+        "speedup_vs_sequential": round(seq["time_to_residual_s"] / elapsed, 3) if seq else None,
+        "roofline": {
+            "bound": "hbm", "kernel": "batch_block_steps_kernel (+ batch_first_step_kernel)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_apply": alg_bytes, "apply_ms": round(apply_ms, 4),
+        },
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,6 +264,10 @@ def main():
         dt = (time.perf_counter() - t0) / reps
         print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
                           "GBps": 2 * nbytes / dt / 1e9}), flush=True)
+        return
+
+    if args.mode == "batch":
+        run_batch(args, dev)
         return
 
     order = 4

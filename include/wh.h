@@ -362,6 +362,17 @@ WH_API wh_status wh_batch_workspace_size(wh_batch *batch, size_t *bytes);
  * batch (no more wh_batch_add). */
 WH_API wh_status wh_batch_finalize(wh_batch *batch, void *workspace, size_t bytes);
 
+/* Batch autotuner: time `applies` batched applications (A v, v = 0) for
+ * every supported (kblock, tile) choice, keep the fastest and return it
+ * (outputs nullable; ms_per_apply = its mean time).  After
+ * wh_batch_finalize; overwrites the problems' scratch vectors (not c^2, f or
+ * solutions held by the caller).  Synchronises. */
+WH_API wh_status wh_batch_autotune(wh_batch *batch, int32_t applies, int32_t *kblock, int32_t *tile,
+                                   double *ms_per_apply);
+
+/* Steps per launch and tile rows in use (defaults resolved). */
+WH_API wh_status wh_batch_get_tuning(const wh_batch *batch, int32_t *kblock, int32_t *tile);
+
 /* out[i] = W_h(v[i], s f_i) for every problem i (host arrays of device
  * pointers, in wh_batch_add order; out[i] may not alias v[i]).  Enqueued on
  * the batch's stream. */

@@ -280,7 +280,7 @@ struct Tuning {
 Tuning resolve_tuning(const wh_ctx *c) {
   const bool fp32 = c->prec == WH_FP32_STATE;
   if (c->kernel == WH_KERNEL_AUTO) {
-    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, fp32 ? 3 : 4, wh::block_default_rows(fp32)};
+    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, 4, wh::block_default_rows(fp32)};
     return {WH_KERNEL_NODE, 1, 0};
   }
   if (c->kernel == WH_KERNEL_BLOCKED_2D)
@@ -1353,7 +1353,7 @@ wh_status bfail(wh_batch *b, wh_status st, const char *fmt, ...) {
 
 void batch_resolve_tuning(wh_batch *b) {
   const bool fp32 = b->prec == WH_FP32_STATE;
-  if (b->K == 0) b->K = fp32 ? 3 : 4;
+  if (b->K == 0) b->K = 4;
   if (b->rows == 0) b->rows = wh::block_default_rows(fp32);
 }
 
@@ -1539,6 +1539,38 @@ wh_status batch_capture(wh_batch *b) {
   return WH_OK;
 }
 
+// Steps per launch and tile rows: pass counts and the per (problem, pass)
+// step coefficients (steps 1 + j K + q and the weights of the levels they
+// produce), uploaded to the coefficient table.
+wh_status batch_set_k(wh_batch *b, int K, int rows) {
+  const size_t P = b->probs.size();
+  std::vector<wh::BlockCoef> coefs;
+  b->coef_off.assign(P, 0);
+  b->passes.assign(P, 0);
+  for (size_t i = 0; i < P; ++i) {
+    wh_ctx *c = b->probs[i];
+    b->passes[i] = batch_passes(c, K);
+    b->coef_off[i] = (int)coefs.size();
+    for (int j = 0; j < b->passes[i]; ++j) {
+      wh::BlockCoef cf{};
+      for (int q = 0; q < K; ++q) {
+        const int64_t n = 1 + (int64_t)j * K + q;
+        if (n + 1 >= (int64_t)c->wts.size()) break;
+        cf.gn[q] = c->frc[(size_t)n];
+        cf.wn[q] = c->wts[(size_t)n + 1];
+      }
+      coefs.push_back(cf);
+    }
+  }
+  b->K = K;
+  b->rows = rows;
+  WH_BHIP(b, hipStreamSynchronize(b->own));
+  WH_BHIP(b, hipMemcpyAsync(b->d_coef, coefs.data(), coefs.size() * sizeof(wh::BlockCoef), hipMemcpyHostToDevice,
+                            b->own));
+  WH_BHIP(b, hipStreamSynchronize(b->own));
+  return WH_OK;
+}
+
 wh_status batch_need(wh_batch *b) {
   if (!b) return WH_EINVAL;
   if (!b->finalized) return bfail(b, WH_ESTATE, "batch not finalized (call wh_batch_finalize)");
@@ -1609,7 +1641,7 @@ wh_status wh_batch_set_tuning(wh_batch *b, int32_t kblock, int32_t tile) {
   if (b->finalized) return bfail(b, WH_ESTATE, "batch already finalized");
   if (b->probs.empty()) return bfail(b, WH_ESTATE, "add problems first");
   const bool fp32 = b->prec == WH_FP32_STATE;
-  const int K = kblock == 0 ? (fp32 ? 3 : 4) : kblock;
+  const int K = kblock == 0 ? 4 : kblock;
   const int rows = tile == 0 ? wh::block_default_rows(fp32) : tile;
   if (K < 2 || !wh::block_config_supported(fp32, b->order, K, rows) || rows > 8 * (fp32 ? 24 : 8))
     return bfail(b, WH_EINVAL, "kblock %d / tile %d not supported for batches", kblock, tile);
@@ -1625,7 +1657,7 @@ wh_status wh_batch_workspace_size(wh_batch *b, size_t *bytes) {
   size_t ncoef = 0;
   int red = 0;
   for (wh_ctx *c : b->probs) {
-    ncoef += (size_t)batch_passes(c, b->K);
+    ncoef += (size_t)batch_passes(c, 2);  // room for any steps-per-launch choice
     red += wh::batch_red_blocks(c->nodes);
   }
   *bytes = batch_layout(b->probs.size(), ncoef, red).total;
@@ -1643,29 +1675,13 @@ wh_status wh_batch_finalize(wh_batch *b, void *workspace, size_t bytes) {
   WH_BHIP(b, hipSetDevice(b->device));
   if (!is_device_ptr(workspace)) return bfail(b, WH_EINVAL, "workspace is not device memory");
   const size_t P = b->probs.size();
-  // per (problem, pass) step coefficients: steps 1 + j K + q, weights of the
-  // levels they produce
-  std::vector<wh::BlockCoef> coefs;
-  b->coef_off.assign(P, 0);
-  b->passes.assign(P, 0);
+  size_t ncoef = 0;
   int red = 0;
-  for (size_t i = 0; i < P; ++i) {
-    wh_ctx *c = b->probs[i];
-    b->passes[i] = batch_passes(c, b->K);
-    b->coef_off[i] = (int)coefs.size();
-    for (int j = 0; j < b->passes[i]; ++j) {
-      wh::BlockCoef cf{};
-      for (int q = 0; q < b->K; ++q) {
-        const int64_t n = 1 + (int64_t)j * b->K + q;
-        if (n + 1 >= (int64_t)c->wts.size()) break;
-        cf.gn[q] = c->frc[(size_t)n];
-        cf.wn[q] = c->wts[(size_t)n + 1];
-      }
-      coefs.push_back(cf);
-    }
+  for (wh_ctx *c : b->probs) {
+    ncoef += (size_t)batch_passes(c, 2);
     red += wh::batch_red_blocks(c->nodes);
   }
-  const BatchLayout L = batch_layout(P, coefs.size(), red);
+  const BatchLayout L = batch_layout(P, ncoef, red);
   char *base = static_cast<char *>(workspace);
   b->d_desc = reinterpret_cast<wh::BatchDesc *>(base + L.desc);
   b->d_first = reinterpret_cast<wh::BatchFirst *>(base + L.first);
@@ -1675,9 +1691,7 @@ wh_status wh_batch_finalize(wh_batch *b, void *workspace, size_t bytes) {
   b->d_vecs_e = reinterpret_cast<wh::BatchVec *>(base + L.vecs_e);
   b->d_part = reinterpret_cast<double *>(base + L.part);
   b->d_sc = reinterpret_cast<double *>(base + L.sc);
-  WH_BHIP(b, hipMemcpyAsync(b->d_coef, coefs.data(), coefs.size() * sizeof(wh::BlockCoef), hipMemcpyHostToDevice,
-                            b->own));
-  WH_BHIP(b, hipStreamSynchronize(b->own));
+  WH_TRY(batch_set_k(b, b->K, b->rows));
   b->finalized = true;
   return WH_OK;
 }
@@ -1848,6 +1862,71 @@ wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, 
   if (st == WH_OK && unconverged)
     st = bfail(b, WH_ENOTCONV, "%d problems did not reach rtol within maxit = %d", unconverged, o->maxit);
   return st;
+}
+
+wh_status wh_batch_autotune(wh_batch *b, int32_t applies, int32_t *kblock, int32_t *tile, double *ms_per_apply) {
+  WH_TRY(batch_need(b));
+  if (applies < 1) return bfail(b, WH_EINVAL, "applies must be >= 1");
+  WH_BHIP(b, hipSetDevice(b->device));
+  const bool fp32 = b->prec == WH_FP32_STATE;
+  const size_t P = b->probs.size();
+  std::vector<const double *> in(P);
+  std::vector<double *> out(P);
+  for (size_t i = 0; i < P; ++i) {
+    wh_ctx *c = b->probs[i];
+    WH_BHIP(b, hipStreamSynchronize(c->stream));
+    WH_BHIP(b, wh::launch_fill(c->tmp, 0.0, c->nodes, b->own));
+    in[i] = c->tmp;
+    out[i] = c->V + 2 * c->ldv;
+  }
+  std::vector<int> all(P);
+  for (size_t i = 0; i < P; ++i) all[i] = (int)i;
+  const int rows_fp64[] = {32, 64}, rows_fp32[] = {96, 192};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  WH_BHIP(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, WH_EDEVICE, "hipEventCreate failed");
+  }
+  int bestK = b->K, bestR = b->rows;
+  double best = INFINITY;
+  wh_status st = WH_OK;
+  for (int K = 2; K <= wh::kMaxBlockSteps && st == WH_OK; ++K) {
+    for (int r = 0; r < 2 && st == WH_OK; ++r) {
+      const int rows = fp32 ? rows_fp32[r] : rows_fp64[r];
+      if (!wh::block_config_supported(fp32, b->order, K, rows)) continue;
+      st = batch_set_k(b, K, rows);
+      if (st == WH_OK) st = batch_select(b, all, in.data(), out.data(), false, nullptr, nullptr, b->own);
+      if (st == WH_OK) st = batch_enqueue_apply(b, false, wh::FINAL_A, b->own);  // warm-up
+      if (st != WH_OK) break;
+      if (hipEventRecord(e0, b->own) != hipSuccess) st = bfail(b, WH_EDEVICE, "hipEventRecord failed");
+      for (int a = 0; a < applies && st == WH_OK; ++a) st = batch_enqueue_apply(b, false, wh::FINAL_A, b->own);
+      float ms = 0.0f;
+      if (st == WH_OK && (hipEventRecord(e1, b->own) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = bfail(b, WH_EDEVICE, "event timing failed");
+      if (st == WH_OK && ms / applies < best) {
+        best = ms / applies;
+        bestK = K;
+        bestR = rows;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  WH_TRY(st);
+  WH_TRY(batch_set_k(b, bestK, bestR));
+  if (kblock) *kblock = bestK;
+  if (tile) *tile = bestR;
+  if (ms_per_apply) *ms_per_apply = best;
+  return WH_OK;
+}
+
+wh_status wh_batch_get_tuning(const wh_batch *b, int32_t *kblock, int32_t *tile) {
+  if (!b) return WH_EINVAL;
+  if (kblock) *kblock = b->K;
+  if (tile) *tile = b->rows;
+  return WH_OK;
 }
 
 }  // extern "C"

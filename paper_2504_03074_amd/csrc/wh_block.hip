@@ -59,6 +59,17 @@ __device__ __forceinline__ int reflect(int i, int n, float &sign) {
   return two_n - m;
 }
 
+// Element e of an array addressed as uniform base + 32-bit byte offset
+// (callers guarantee e * sizeof(U) < 2^32).
+template <typename U>
+__device__ __forceinline__ U ld_at(const U *__restrict__ p, uint32_t e) {
+  return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(p) + e * (uint32_t)sizeof(U));
+}
+template <typename U>
+__device__ __forceinline__ void st_at(U *__restrict__ p, uint32_t e, U x) {
+  *reinterpret_cast<U *>(reinterpret_cast<char *>(p) + e * (uint32_t)sizeof(U)) = x;
+}
+
 // XCD-aware tile order: consecutive work-groups are dispatched round-robin
 // over the 8 XCDs; give each XCD a contiguous run of tiles so that the halo
 // re-reads of neighbouring tiles hit the same L2.
@@ -69,12 +80,12 @@ __device__ __forceinline__ int xcd_tile_order(int b, int nblk) {
 
 // K (ksteps <= K) leapfrog steps of one tile (tx, ty) of one grid: the body
 // shared by the single-grid and the batched kernels.
-template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
-__device__ __forceinline__ void advance_tile(
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR, bool INNER>
+__device__ __forceinline__ void advance_tile_impl(
     const StepGeom &g, int ksteps, int tx, int ty, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
     T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
     const T *__restrict__ fg, const BlockCoef &coef, int mode, const double *__restrict__ v,
-    double *__restrict__ out) {
+    double *__restrict__ out, T (*__restrict__ halo)[NW][2][P / 2][64]) {
   constexpr int R = P / 2;
   constexpr int H = K * R;
   constexpr int OX = 64 - 2 * H;
@@ -83,44 +94,68 @@ __device__ __forceinline__ void advance_tile(
   static_assert(RS >= R, "each wave must hold at least r rows");
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform: keep it (and everything derived from it) in
+  // scalar registers so per-row ownership tests are scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x0 = tx * OX, y0 = ty * OY;
   const int gx = x0 - H + lane;
   const int gy0 = y0 - H + wave * RS;
-
-  __shared__ T halo[2][NW][2][R][64];
 
   T A[RS], B[RS], C2[RS], F[RS];
   double ACC[RS];
   uint32_t own = 0;  // bit q: row q of this lane is an owned interior node
 
-  float sx = 1.0f;
-  const int ix = reflect(gx, g.nx, sx);
-  const bool col_owned = lane >= H && lane < H + OX && gx <= g.nx;
-  const bool col_wall = ix == 0 || ix == g.nx;
+  // Inner tiles (tile and halo strictly inside the walls, the usual case)
+  // need no reflection and hold no wall node: every row is addressed by one
+  // 32-bit byte offset shared by all arrays (uniform base + offset).
+  const bool col_in = lane >= H && lane < H + OX;
+  const uint32_t base = INNER ? (uint32_t)gx + (uint32_t)gy0 * (uint32_t)g.sy : 0u;
+  if constexpr (INNER) {
 #pragma unroll
-  for (int q = 0; q < RS; ++q) {
-    float s = sx;
-    const int gy = gy0 + q;
-    const int iy = reflect(gy, g.ny, s);
-    const int64_t id = (int64_t)ix + (int64_t)iy * g.sy;
-    const T sg = static_cast<T>(s);
-    B[q] = sg * in_prev[id];
-    A[q] = sg * in_cur[id];
-    C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
-    F[q] = FORCE ? sg * fg[id] : T(0);
-    const int r = wave * RS + q;
-    const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
-    const bool wall = col_wall || iy == 0 || iy == g.ny;
-    ACC[q] = 0.0;
-    if (in_tile && !wall) {
-      own |= 1u << q;
-      ACC[q] = acc[id];
-    } else if (in_tile) {
-      // wall node owned by this tile: its outputs are exactly 0
-      out_prev[id] = T(0);
-      out_cur[id] = T(0);
-      if (mode != ACCUMULATE) out[id] = 0.0;
+    for (int q = 0; q < RS; ++q) {
+      const uint32_t e = base + (uint32_t)q * (uint32_t)g.sy;
+      B[q] = ld_at(in_prev, e);
+      A[q] = ld_at(in_cur, e);
+      C2[q] = CVAR ? ld_at(c2g, e) : static_cast<T>(g.c2const);
+      F[q] = FORCE ? ld_at(fg, e) : T(0);
+      const int r = wave * RS + q;
+      ACC[q] = 0.0;
+      if (r >= H && r < H + OY) {
+        if (col_in) {
+          own |= 1u << q;
+          ACC[q] = ld_at(acc, e);
+        }
+      }
+    }
+  } else {
+    float sx = 1.0f;
+    const int ix = reflect(gx, g.nx, sx);
+    const bool col_owned = col_in && gx <= g.nx;
+    const bool col_wall = ix == 0 || ix == g.nx;
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      float s = sx;
+      const int gy = gy0 + q;
+      const int iy = reflect(gy, g.ny, s);
+      const int64_t id = (int64_t)ix + (int64_t)iy * g.sy;
+      const T sg = static_cast<T>(s);
+      B[q] = sg * in_prev[id];
+      A[q] = sg * in_cur[id];
+      C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
+      F[q] = FORCE ? sg * fg[id] : T(0);
+      const int r = wave * RS + q;
+      const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
+      const bool wall = col_wall || iy == 0 || iy == g.ny;
+      ACC[q] = 0.0;
+      if (in_tile && !wall) {
+        own |= 1u << q;
+        ACC[q] = acc[id];
+      } else if (in_tile) {
+        // wall node owned by this tile: its outputs are exactly 0
+        out_prev[id] = T(0);
+        out_cur[id] = T(0);
+        if (mode != ACCUMULATE) out[id] = 0.0;
+      }
     }
   }
 
@@ -174,6 +209,22 @@ __device__ __forceinline__ void advance_tile(
 
   // after ksteps steps the newest level is in B if ksteps is odd, else in A
   const bool odd = ksteps & 1;
+  if constexpr (INNER) {
+    if (col_in) {
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        const int r = wave * RS + q;
+        if (r < H || r >= H + OY) continue;
+        const uint32_t e = base + (uint32_t)q * (uint32_t)g.sy;
+        st_at(out_cur, e, odd ? B[q] : A[q]);
+        st_at(out_prev, e, odd ? A[q] : B[q]);
+        if (mode == ACCUMULATE) st_at(acc, e, ACC[q]);
+        else if (mode == FINAL_FILTER) st_at(out, e, ACC[q]);
+        else st_at(out, e, ld_at(v, e) - ACC[q]);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < RS; ++q) {
     if (!((own >> q) & 1u)) continue;
@@ -187,15 +238,39 @@ __device__ __forceinline__ void advance_tile(
 }
 
 template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
+__device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, int tx, int ty,
+                                             const T *__restrict__ in_prev, const T *__restrict__ in_cur,
+                                             T *__restrict__ out_prev, T *__restrict__ out_cur,
+                                             double *__restrict__ acc, const T *__restrict__ c2g,
+                                             const T *__restrict__ fg, const BlockCoef &coef, int mode,
+                                             const double *__restrict__ v, double *__restrict__ out,
+                                             T (*__restrict__ halo)[NW][2][P / 2][64]) {
+  constexpr int H = K * (P / 2);
+  constexpr int OX = 64 - 2 * H;
+  constexpr int OY = NW * RS - 2 * H;
+  const int x0 = tx * OX - H, y0 = ty * OY - H;
+  // uniform over the work-group: one of the two bodies runs
+  const bool inner = x0 >= 1 && x0 + 63 <= g.nx - 1 && y0 >= 1 && y0 + NW * RS - 1 <= g.ny - 1 &&
+                     g.nodes <= (int64_t(1) << 28);
+  if (inner)
+    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur, acc,
+                                                          c2g, fg, coef, mode, v, out, halo);
+  else
+    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur,
+                                                           acc, c2g, fg, coef, mode, v, out, halo);
+}
+
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
 __global__ __launch_bounds__(64 * NW) void block_steps_kernel(
     StepGeom g, int ksteps, int tiles_x, int tiles_total, const T *__restrict__ in_prev,
     const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
     const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
     double *__restrict__ out) {
+  __shared__ T halo[2][NW][2][P / 2][64];  // y-halo rows, double-buffered over steps
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= tiles_total) return;
   advance_tile<T, P, K, RS, NW, FORCE, CVAR>(g, ksteps, tile % tiles_x, tile / tiles_x, in_prev, in_cur, out_prev,
-                                             out_cur, acc, c2g, fg, coef, mode, v, out);
+                                             out_cur, acc, c2g, fg, coef, mode, v, out, halo);
 }
 
 // Batched pass: work-group -> (problem, tile) through the prefix sums of the
@@ -206,6 +281,7 @@ __global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchD
                                                                     const int *__restrict__ tile_prefix, int nactive,
                                                                     int pass, const BlockCoef *__restrict__ coefs,
                                                                     int final_mode) {
+  __shared__ T halo[2][NW][2][P / 2][64];
   const int total = tile_prefix[nactive];
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= total) return;
@@ -228,10 +304,10 @@ __global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchD
   const int tx = local % d.tiles_x, ty = local / d.tiles_x;
   if (d.c2)
     advance_tile<T, P, K, RS, NW, FORCE, true>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, static_cast<const T *>(d.c2),
-                                               static_cast<const T *>(d.f), coef, mode, d.v, d.out);
+                                               static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
   else
     advance_tile<T, P, K, RS, NW, FORCE, false>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, nullptr,
-                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out);
+                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
 }
 
 template <typename T, int P, int K, int RS, int NW>

@@ -122,6 +122,9 @@ def _load():
         "wh_batch_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "wh_batch_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "wh_batch_finalize": (st, [_vp, _vp, ctypes.c_size_t]),
+        "wh_batch_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+        "wh_batch_get_tuning": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "wh_batch_apply": (st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32]),
         "wh_batch_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(_vp),
                                 ctypes.POINTER(wh_solve_info)]),
@@ -372,6 +375,19 @@ def wh_batch_finalize(batch, ptr: int, nbytes: int):
     _bcheck(batch, _load().wh_batch_finalize(batch, _vp(ptr), nbytes))
 
 
+def wh_batch_autotune(batch, applies=3):
+    k, t, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _bcheck(batch, _load().wh_batch_autotune(batch, int(applies), ctypes.byref(k), ctypes.byref(t),
+                                             ctypes.byref(ms)))
+    return k.value, t.value, ms.value
+
+
+def wh_batch_get_tuning(batch):
+    k, t = ctypes.c_int32(), ctypes.c_int32()
+    _bcheck(batch, _load().wh_batch_get_tuning(batch, ctypes.byref(k), ctypes.byref(t)))
+    return k.value, t.value
+
+
 def wh_batch_apply(batch, v: list, out: list, with_forcing: bool):
     _bcheck(batch, _load().wh_batch_apply(batch, _ptrs(v), _ptrs(out), int(bool(with_forcing))))
 
@@ -569,6 +585,15 @@ class Batch:
             except Exception:
                 pass
             self.batch = None
+
+    def autotune(self, applies=3):
+        """Time every (kblock, tile) choice on the batch and keep the fastest."""
+        k, t, ms = wh_batch_autotune(self.batch, applies)
+        return dict(kblock=k, tile=t, ms_per_apply=ms)
+
+    def tuning(self):
+        k, t = wh_batch_get_tuning(self.batch)
+        return dict(kblock=k, tile=t)
 
     def apply(self, vs, with_forcing=True, outs=None):
         outs = [s.new() for s in self.solvers] if outs is None else outs

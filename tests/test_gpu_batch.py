@@ -116,6 +116,20 @@ def test_batch_apply_tunings(torch, kblock, tile):
         assert _rel(o.cpu().numpy(), want) <= TOL["fp64"], p.grid.n
 
 
+def test_batch_autotune_then_apply(torch):
+    from paper_2504_03074_amd import Batch
+    _say("[batch autotune]")
+    probs = _mix(4, seed0=620)
+    batch = Batch([p.solver("fp64", 4) for p in probs])
+    best = batch.autotune(1)
+    assert best["kblock"] in (2, 3, 4) and best["tile"] in (32, 64) and best["ms_per_apply"] > 0
+    assert batch.tuning() == dict(kblock=best["kblock"], tile=best["tile"])
+    outs = batch.apply([_to_dev(torch, p.v) for p in probs], with_forcing=True)
+    for p, o in zip(probs, outs):
+        want = oc.apply(p.grid, p.c2, p.f, p.v, p.tp, with_forcing=True)
+        assert _rel(o.cpu().numpy(), want) <= TOL["fp64"], p.grid.n
+
+
 def test_batch_apply_repeated_with_other_inputs(torch):
     """The descriptor tables are rebuilt per call: a second call with other
     inputs must not see the first call's pointers."""
