@@ -330,6 +330,56 @@ WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
 WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
 
 /* ------------------------------------------------------------------------
+ * Discrete adjoint (FP64-state contexts).
+ *
+ * One application Y = W_h(v, f) (the explicit scheme of Sec. 4.2.1 and the
+ * trapezoid filter) is differentiated exactly, at fixed time parameters
+ * (dt, N_t, omega_e, alpha: fix N_t with wh_set_frequency's nt_override when
+ * c^2 changes).  With Z^n the adjoint of level W^n, the transpose of the
+ * leapfrog runs backwards in time; because Delta_h is symmetric,
+ * c^2 Z^n obeys the forward leapfrog recursion forced by w_n c^2 lam.  The
+ * forward levels needed on the way back are recomputed from checkpoints
+ * taken every s = ceil(sqrt(N)) levels (N = N_t * periods), so memory is
+ * O(sqrt(N)) fields and the cost is about two extra forward sweeps.
+ *
+ * The fixed point of Alg. 1, v* = W_h(v*, f), gives for a misfit J(v*):
+ *   (I - S)^T lam = dJ/dv,   dJ/dc^2 = d/dc^2 [lam . W_h(v*, f)],
+ *   dJ/df = d/df [lam . W_h(v*, f)].
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace the adjoint needs for the current grid and
+ * frequency (checkpoints, recomputed segment, adjoint levels). */
+WH_API wh_status wh_adjoint_workspace_size(wh_ctx *ctx, size_t *bytes);
+
+/* Bind (or, with NULL, unbind) the caller-owned adjoint workspace
+ * (256-byte aligned device memory of at least wh_adjoint_workspace_size). */
+WH_API wh_status wh_bind_adjoint_workspace(wh_ctx *ctx, void *ptr, size_t bytes);
+
+/* Sensitivities of lam . W_h(v, f) (f = the context's source) with respect
+ * to c^2 (grad_c2), f (grad_f) and v (grad_v = S^T lam); node arrays on the
+ * device, each output nullable, written (not accumulated), 0 on walls;
+ * outputs distinct and not aliasing v or lam.  Wall values of v and lam are
+ * ignored.  Uses the solver workspace's stepping buffers and the adjoint
+ * workspace (WH_ENOMEM if missing or too small).  Enqueued on the stream. */
+WH_API wh_status wh_gradient(wh_ctx *ctx, const double *v, const double *lam, double *grad_c2, double *grad_f,
+                             double *grad_v);
+
+/* Solve (I - S_h)^T lam = g by the method of opts: (I - S)^T equals
+ * C^{-1} (I - S) C with C = diag(c^2), so (I - S) mu = C g is solved with
+ * wh_solve_rhs's machinery from the guess C lam and lam = mu / c^2 is
+ * returned.  lam (device) holds the guess on entry; info and statuses as for
+ * wh_solve (residuals refer to the mu system).  Synchronises. */
+WH_API wh_status wh_solve_adjoint(wh_ctx *ctx, const wh_solve_opts *opts, const double *g, double *lam,
+                                  wh_solve_info *info);
+
+/* Receiver misfit J = 1/2 sum_r (u[idx_r] - data_r)^2 over nrec receivers
+ * (idx: flat node indices, int64, device; data: device) and, if grad is not
+ * NULL, grad = dJ/du (device node array, overwritten; repeated indices add
+ * up).  WH_EINVAL if any index lies outside the grid.  Synchronises. */
+WH_API wh_status wh_receiver_misfit(wh_ctx *ctx, const double *u, const int64_t *idx, const double *data,
+                                    int32_t nrec, double *J, double *grad);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent 2-D problems advanced together.  Each problem is
  * a fully configured context (grid, workspace sized for restart >= 2, c^2,
  * source, frequency; same order and precision across the batch; different

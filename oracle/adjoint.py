@@ -123,10 +123,11 @@ def parameter_gradient(grid, c2, f, v, lam, tp):
     return _interior(grid, d_c2), _interior(grid, d_f), Z[0]
 
 
-def solve_adjoint(grid, c2, g, tp, rtol=1e-13, maxit=5000):
-    """lam with (I - S)^T lam = g (walls of g ignored), by GMRES on the
-    operator lam -> lam - S^T lam (library Krylov routine)."""
-    import scipy.sparse.linalg as sla
+def solve_adjoint(grid, c2, g, tp, rtol=1e-12, maxit=200, dense_limit=2500):
+    """lam with (I - S)^T lam = g (walls of g ignored).  Up to `dense_limit`
+    unknowns the matrix I - S^T is assembled column by column from
+    apply_transpose and solved directly (LAPACK); beyond that, GMRES on the
+    operator (library Krylov routine, relative tolerance rtol)."""
     mask = oc.interior_mask(grid)
     m = int(mask.sum())
 
@@ -135,11 +136,21 @@ def solve_adjoint(grid, c2, g, tp, rtol=1e-13, maxit=5000):
         full[mask] = x
         return (full - apply_transpose(grid, c2, full, tp))[mask]
 
-    op = sla.LinearOperator((m, m), matvec=mv, dtype=np.float64)
     rhs = np.asarray(g, dtype=np.float64)[mask]
-    x, info = sla.gmres(op, rhs, rtol=rtol, atol=0.0, restart=min(m, 200), maxiter=maxit)
-    if info != 0:
-        raise RuntimeError(f"adjoint GMRES did not converge (info={info})")
+    if m <= dense_limit:
+        M = np.empty((m, m))
+        e = np.zeros(m)
+        for i in range(m):
+            e[i] = 1.0
+            M[:, i] = mv(e)
+            e[i] = 0.0
+        x = np.linalg.solve(M, rhs)
+    else:
+        import scipy.sparse.linalg as sla
+        op = sla.LinearOperator((m, m), matvec=mv, dtype=np.float64)
+        x, info = sla.gmres(op, rhs, rtol=rtol, atol=0.0, restart=200, maxiter=maxit)
+        if info != 0:
+            raise RuntimeError(f"adjoint GMRES did not converge (info={info})")
     lam = np.zeros(grid.shape)
     lam[mask] = x
     return lam

@@ -47,6 +47,8 @@ struct wh_ctx {
   std::vector<double> frc;   // -dt^2 cos(omega_e t^n), n = 0..N-1
 
   int kernel = WH_KERNEL_AUTO, kblock = 0, tile = 0;
+  char *adj = nullptr;  // adjoint workspace (checkpoints, reverse sweep)
+  size_t adj_bytes = 0;
   double *pinned = nullptr;  // host staging for reduction results
   size_t pinned_count = 0;
 
@@ -873,7 +875,8 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
 // c->b <- the right-hand side: the given device vector, or b = W_h(0, f).
 static wh_status make_rhs(wh_ctx *c, const double *rhs, int *applies) {
   if (rhs) {
-    WH_HIP(c, hipMemcpyAsync(c->b, rhs, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (rhs != c->b)
+      WH_HIP(c, hipMemcpyAsync(c->b, rhs, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
     return WH_OK;
   }
   WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
@@ -1287,6 +1290,201 @@ wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, con
     st = fail(hi, WH_ENOTCONV, "mixed-precision refinement reached maxit = %d at relative residual %g",
               outer->maxit, rel);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// discrete adjoint: gradient of lam . W_h(v, f) and the adjoint fixed-point
+// solve
+// ---------------------------------------------------------------------------
+namespace {
+
+// Checkpointing of the forward levels W^0..W^{N-1} of one application: pairs
+// (W^k, W^{k+1}) at k = j s (s = ceil(sqrt(N)), j < ncp = ceil(N/s)); the
+// reverse sweep recomputes one segment of s levels at a time.
+struct AdjLayout {
+  int64_t N;
+  int seg, ncp;
+  size_t stride, total;
+  size_t buffers;
+};
+
+AdjLayout adjoint_layout(const wh_ctx *c) {
+  AdjLayout L{};
+  L.N = (int64_t)c->tp.nt * c->tp.periods;
+  L.seg = (int)std::ceil(std::sqrt((double)L.N));
+  if ((int64_t)L.seg * L.seg < L.N) ++L.seg;
+  L.ncp = (int)((L.N + L.seg - 1) / L.seg);
+  L.stride = align256((size_t)c->nodes * 8);
+  // checkpoint pairs, segment levels beyond the pair, two adjoint levels,
+  // c^2 lam and the two sensitivity accumulators
+  L.buffers = (size_t)2 * L.ncp + (size_t)std::max(L.seg - 2, 0) + 2 + 3;
+  L.total = L.buffers * L.stride;
+  return L;
+}
+
+wh_status need_fp64(wh_ctx *c, const char *what) {
+  if (c->prec != WH_FP64) return fail(c, WH_EINVAL, "%s needs an FP64-state context", what);
+  return WH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wh_status wh_adjoint_workspace_size(wh_ctx *c, size_t *bytes) {
+  WH_TRY(need(c, true, false, false, false, true));
+  if (!bytes) return fail(c, WH_EINVAL, "bytes is NULL");
+  *bytes = adjoint_layout(c).total;
+  return WH_OK;
+}
+
+wh_status wh_bind_adjoint_workspace(wh_ctx *c, void *ptr, size_t bytes) {
+  WH_TRY(need(c, true, false, false, false, false));
+  if (!ptr) {
+    c->adj = nullptr;
+    c->adj_bytes = 0;
+    return WH_OK;
+  }
+  if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return fail(c, WH_EINVAL, "adjoint workspace must be 256-byte aligned");
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, ptr, "adjoint workspace"));
+  c->adj = static_cast<char *>(ptr);
+  c->adj_bytes = bytes;
+  return WH_OK;
+}
+
+wh_status wh_gradient(wh_ctx *c, const double *v, const double *lam, double *grad_c2, double *grad_f,
+                      double *grad_v) {
+  WH_TRY(need(c, true, true, true, true, true));
+  WH_TRY(need_fp64(c, "wh_gradient"));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, v, "v"));
+  WH_TRY(check_dev(c, lam, "lam"));
+  double *outs[3] = {grad_c2, grad_f, grad_v};
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i]) continue;
+    WH_TRY(check_dev(c, outs[i], "gradient output"));
+    if (outs[i] == v || outs[i] == lam) return fail(c, WH_EINVAL, "gradient outputs may not alias v or lam");
+    for (int k = 0; k < i; ++k)
+      if (outs[k] == outs[i]) return fail(c, WH_EINVAL, "gradient outputs must be distinct");
+  }
+  const AdjLayout L = adjoint_layout(c);
+  if (!c->adj || c->adj_bytes < L.total)
+    return fail(c, WH_ENOMEM, "adjoint workspace of %zu bytes needed (wh_adjoint_workspace_size)", L.total);
+  auto buf = [&](size_t i) { return reinterpret_cast<double *>(c->adj + i * L.stride); };
+  auto cpA = [&](int j) { return buf((size_t)2 * j); };
+  auto cpB = [&](int j) { return buf((size_t)2 * j + 1); };
+  const size_t seg0 = (size_t)2 * L.ncp, zbase = seg0 + (size_t)std::max(L.seg - 2, 0);
+  double *zc = buf(zbase), *zp = buf(zbase + 1), *clam = buf(zbase + 2), *gf = buf(zbase + 3),
+         *gc = buf(zbase + 4);
+  const double dt2 = c->tp.dt * c->tp.dt;
+  const wh::StepGeom g = geometry(c, dt2), half = geometry(c, 0.5 * dt2);
+  const double *c2p = c->c2_is_const ? nullptr : static_cast<const double *>(c->c2);
+  const double *f = static_cast<const double *>(c->f);
+  const size_t nb = (size_t)c->nodes * 8;
+  hipStream_t s = c->stream;
+  auto step = [&](const double *cur, double *prev_next, int64_t from) -> wh_status {
+    // W^{from+1} = 2 W^from - W^{from-1} + c^2 dt^2 Delta_h W^from + frc[from] f
+    WH_HIP(c, wh::launch_step(false, g, cur, prev_next, c->acc, c2p, f, c->frc[(size_t)from], 0.0, wh::ACCUMULATE,
+                              nullptr, nullptr, s));
+    return WH_OK;
+  };
+
+  // forward sweep: first step into checkpoint 0, then roll two levels and
+  // copy the pairs at the checkpoints (the accumulator is scratch here)
+  WH_HIP(c, wh::launch_first_step(false, half, v, cpA(0), cpB(0), c->acc, c2p, f, -0.5 * dt2, 0.0, 0.0, s));
+  if (L.ncp > 1) {
+    double *prev = static_cast<double *>(c->W[0]), *cur = static_cast<double *>(c->W[1]);
+    WH_HIP(c, hipMemcpyAsync(prev, cpA(0), nb, hipMemcpyDeviceToDevice, s));
+    WH_HIP(c, hipMemcpyAsync(cur, cpB(0), nb, hipMemcpyDeviceToDevice, s));
+    const int64_t last = (int64_t)(L.ncp - 1) * L.seg + 1;
+    for (int64_t m = 2; m <= last; ++m) {
+      WH_TRY(step(cur, prev, m - 1));
+      std::swap(prev, cur);  // cur = W^m
+      if (m % L.seg == 0) WH_HIP(c, hipMemcpyAsync(cpA((int)(m / L.seg)), cur, nb, hipMemcpyDeviceToDevice, s));
+      if (m % L.seg == 1 && m > L.seg)
+        WH_HIP(c, hipMemcpyAsync(cpB((int)((m - 1) / L.seg)), cur, nb, hipMemcpyDeviceToDevice, s));
+    }
+  }
+
+  // reverse sweep, one segment at a time from the last
+  WH_HIP(c, wh::launch_fill(zc, 0.0, c->nodes, s));
+  WH_HIP(c, wh::launch_fill(zp, 0.0, c->nodes, s));
+  WH_HIP(c, wh::launch_fill(gf, 0.0, c->nodes, s));
+  WH_HIP(c, wh::launch_fill(gc, 0.0, c->nodes, s));
+  WH_HIP(c, wh::launch_scale_c2(g, c2p, lam, clam, false, s));
+  std::vector<double *> lev((size_t)L.seg);
+  for (int j = L.ncp - 1; j >= 0; --j) {
+    const int64_t k = (int64_t)j * L.seg;
+    const int64_t top = std::min<int64_t>(k + L.seg, L.N);
+    lev[0] = cpA(j);
+    if (top - k > 1) lev[1] = cpB(j);
+    for (int64_t i = 2; i < top - k; ++i) {
+      double *dst = buf(seg0 + (size_t)(i - 2));
+      WH_HIP(c, hipMemcpyAsync(dst, lev[(size_t)i - 2], nb, hipMemcpyDeviceToDevice, s));
+      WH_TRY(step(lev[(size_t)i - 1], dst, k + i - 1));
+      lev[(size_t)i] = dst;
+    }
+    for (int64_t n = top; n > k; --n) {
+      const bool first = n == 1;
+      const double gam = first ? -0.5 * dt2 : c->frc[(size_t)(n - 1)];
+      WH_HIP(c, wh::launch_adjoint_step(g, zc, zp, c2p, clam, c->wts[(size_t)n], lev[(size_t)(n - 1 - k)], gam,
+                                        first ? 0.5 : 1.0, gf, gc, s));
+      std::swap(zc, zp);  // zc = Zh^n, zp = Zh^{n+1}
+    }
+  }
+  if (grad_v) WH_HIP(c, wh::launch_adjoint_first(half, zc, zp, c2p, clam, c->wts[0], grad_v, s));
+  if (grad_c2) WH_HIP(c, wh::launch_scale_c2(g, c2p, gc, grad_c2, true, s));
+  if (grad_f) WH_HIP(c, wh::launch_scale_c2(g, c2p, gf, grad_f, true, s));
+  return WH_OK;
+}
+
+wh_status wh_solve_adjoint(wh_ctx *c, const wh_solve_opts *o, const double *g, double *lam, wh_solve_info *info) {
+  WH_TRY(need(c, true, true, true, false, true));
+  WH_TRY(need_fp64(c, "wh_solve_adjoint"));
+  WH_TRY(check_opts(c, o));
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, g, "g"));
+  WH_TRY(check_dev(c, lam, "lam"));
+  if (g == lam) return fail(c, WH_EINVAL, "lam may not alias g");
+  // (I - S)^T = C^{-1} (I - S) C, C = diag(c^2): solve (I - S) mu = C g,
+  // starting from C lam, then lam = mu / c^2
+  const wh::StepGeom g1 = geometry(c, 1.0);
+  const double *c2p = c->c2_is_const ? nullptr : static_cast<const double *>(c->c2);
+  WH_HIP(c, wh::launch_scale_c2(g1, c2p, g, c->b, false, c->stream));
+  WH_HIP(c, wh::launch_scale_c2(g1, c2p, lam, lam, false, c->stream));
+  const wh_status st = solve_dispatch(c, o, c->b, lam, info);
+  WH_HIP(c, wh::launch_scale_c2(g1, c2p, lam, lam, true, c->stream));
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  return st;
+}
+
+wh_status wh_receiver_misfit(wh_ctx *c, const double *u, const int64_t *idx, const double *data, int32_t nrec,
+                             double *J, double *grad) {
+  WH_TRY(need(c, true, true, false, false, false));
+  if (!J) return fail(c, WH_EINVAL, "J is NULL");
+  if (nrec < 0) return fail(c, WH_EINVAL, "nrec must be >= 0");
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, u, "u"));
+  if (nrec > 0) {
+    WH_TRY(check_dev(c, idx, "idx"));
+    WH_TRY(check_dev(c, data, "data"));
+  }
+  if (grad) {
+    WH_TRY(check_dev(c, grad, "grad"));
+    if (grad == u) return fail(c, WH_EINVAL, "grad may not alias u");
+    WH_HIP(c, wh::launch_fill(grad, 0.0, c->nodes, c->stream));
+  }
+  double out[2] = {0.0, 0.0};
+  if (nrec > 0) {
+    WH_HIP(c, wh::launch_misfit(u, idx, data, nrec, c->nodes, grad, c->scal, c->stream));
+    WH_TRY(fetch_scalars(c, 0, 2, out));
+    if (out[1] > 0.0) return fail(c, WH_EINVAL, "%.0f receiver indices lie outside the grid", out[1]);
+  }
+  *J = out[0];
+  return WH_OK;
 }
 
 }  // extern "C"

@@ -173,6 +173,24 @@ hipError_t launch_interior_stats(const StepGeom &g, const double *src, double *p
 hipError_t launch_helmholtz_residual(const StepGeom &g_unscaled, const double *u, const void *c2, bool fp32_c2,
                                      const void *f, bool fp32_f, double omega2, double *res, hipStream_t s);
 hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t s);
+
+// Discrete adjoint (FP64 state).  One reverse-time step: zprev_next <-
+// 2 zcur - zprev_next + c2 (g-scaled Delta_h zcur) + wn clam; then
+// gf += gam * new (gf nullable), gc += kap * new * (g-scaled Delta_h wprev)
+// (gc nullable).  c2 null = constant g.c2const.
+hipError_t launch_adjoint_step(const StepGeom &g, const double *zcur, double *zprev_next, const double *c2,
+                               const double *clam, double wn, const double *wprev, double gam, double kap, double *gf,
+                               double *gc, hipStream_t s);
+// out = (w0 clam + z1 + c2 (half-scaled Delta_h z1) - z2) / c2, walls 0
+hipError_t launch_adjoint_first(const StepGeom &half, const double *z1, const double *z2, const double *c2,
+                                const double *clam, double w0, double *out, hipStream_t s);
+// out = in * c2 or in / c2 (divide) on interior nodes, 0 on walls
+hipError_t launch_scale_c2(const StepGeom &g, const double *c2, const double *in, double *out, bool divide,
+                           hipStream_t s);
+// receiver misfit: out[0] = J, out[1] = count of out-of-range indices;
+// grad (nullable, pre-zeroed) += residuals at the receiver nodes
+hipError_t launch_misfit(const double *u, const int64_t *idx, const double *data, int nrec, int64_t nodes,
+                         double *grad, double *out, hipStream_t s);
 // Overwrite the wall nodes of a state-precision node array with `value`.
 hipError_t launch_set_walls(bool fp32, const StepGeom &g, void *a, double value, hipStream_t s);
 

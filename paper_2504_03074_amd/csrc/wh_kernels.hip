@@ -867,4 +867,155 @@ hipError_t launch_batch_residual(const BatchVec *vecs, int nprob, int total_bloc
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// discrete adjoint (FP64)
+//
+// With Z^n the adjoint of level W^n of one application and Zh^n = c^2 Z^n,
+// the transpose of the leapfrog is the same leapfrog run backwards in time:
+//   Zh^n = 2 Zh^{n+1} - Zh^{n+2} + c^2 (dt^2 Delta_h Zh^{n+1}) + w_n (c^2 lam),
+// because Delta_h (with the odd wall reflection) is symmetric.  The
+// sensitivities are collected as the sweep passes each level:
+//   gf += gamma_{n-1} Zh^n,   gc += kappa_{n-1} Zh^n (dt^2 Delta_h W^{n-1}),
+// and divided by c^2 at the end.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void adjoint_step_kernel(
+    StepGeom g, const double *__restrict__ zcur, double *__restrict__ zprev_next, const double *__restrict__ c2,
+    const double *__restrict__ clam, double wn, const double *__restrict__ wprev, double gam, double kap,
+    double *__restrict__ gf, double *__restrict__ gc) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+  const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
+  if (wall) {
+    zprev_next[idx] = 0.0;
+    return;
+  }
+  const Coef<double> c = coef_of<double>(g);
+  const double c2v = c2 ? c2[idx] : g.c2const;
+  const double zn =
+      2.0 * zcur[idx] - zprev_next[idx] + c2v * stencil<double, DIM, P>(zcur, i, j, k, idx, g, c) + wn * clam[idx];
+  zprev_next[idx] = zn;
+  if (gf) gf[idx] += gam * zn;
+  if (gc) gc[idx] += kap * zn * stencil<double, DIM, P>(wprev, i, j, k, idx, g, c);
+}
+
+// Adjoint of the initial level: out = (w_0 c^2 lam + Zh^1 + c^2 (dt^2/2)
+// Delta_h Zh^1 - Zh^2) / c^2, the sensitivity to v (half-scaled geometry).
+template <int DIM, int P>
+__global__ __launch_bounds__(kBlockX *kBlockY) void adjoint_first_kernel(
+    StepGeom half, const double *__restrict__ z1, const double *__restrict__ z2, const double *__restrict__ c2,
+    const double *__restrict__ clam, double w0, double *__restrict__ out) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > half.nx || j > half.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * half.sy + (int64_t)k * half.sz;
+  const bool wall = i == 0 || i == half.nx || j == 0 || j == half.ny || (DIM == 3 && (k == 0 || k == half.nz));
+  if (wall) {
+    out[idx] = 0.0;
+    return;
+  }
+  const Coef<double> c = coef_of<double>(half);
+  const double c2v = c2 ? c2[idx] : half.c2const;
+  const double zh = w0 * clam[idx] + z1[idx] + c2v * stencil<double, DIM, P>(z1, i, j, k, idx, half, c) - z2[idx];
+  out[idx] = zh / c2v;
+}
+
+// out = in * c^2 (divide = false) or in / c^2 on interior nodes, 0 on walls
+template <int DIM>
+__global__ __launch_bounds__(kBlockX *kBlockY) void scale_c2_kernel(StepGeom g, const double *__restrict__ c2,
+                                                                   const double *__restrict__ in,
+                                                                   double *__restrict__ out, int divide) {
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k = (DIM == 3) ? (int)blockIdx.z : 0;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t idx = (int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+  const bool wall = i == 0 || i == g.nx || j == 0 || j == g.ny || (DIM == 3 && (k == 0 || k == g.nz));
+  if (wall) {
+    out[idx] = 0.0;
+    return;
+  }
+  const double c2v = c2 ? c2[idx] : g.c2const;
+  out[idx] = divide ? in[idx] / c2v : in[idx] * c2v;
+}
+
+// Receiver misfit: one work-group.  res_r = u[idx_r] - d_r; out[0] = 1/2
+// sum res_r^2, out[1] = number of indices outside [0, nodes); grad (nullable,
+// zeroed by the caller) receives res_r at idx_r.
+__global__ __launch_bounds__(kRedThreads) void misfit_kernel(const double *__restrict__ u,
+                                                             const int64_t *__restrict__ idx,
+                                                             const double *__restrict__ data, int nrec,
+                                                             int64_t nodes, double *__restrict__ grad,
+                                                             double *__restrict__ out) {
+  __shared__ double sm[4];
+  double s = 0.0, bad = 0.0;
+  for (int r = threadIdx.x; r < nrec; r += kRedThreads) {
+    const int64_t e = idx[r];
+    if (e < 0 || e >= nodes) {
+      bad += 1.0;
+      continue;
+    }
+    const double res = u[e] - data[r];
+    s += res * res;
+    if (grad) atomicAdd(grad + e, res);
+  }
+  s = block_sum(s, sm);
+  bad = block_sum(bad, sm);
+  if (threadIdx.x == 0) {
+    out[0] = 0.5 * s;
+    out[1] = bad;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(const StepGeom &g, const double *zcur, double *zprev_next, const double *c2,
+                               const double *clam, double wn, const double *wprev, double gam, double kap, double *gf,
+                               double *gc, hipStream_t s) {
+  const dim3 grid = node_grid(g), block(kBlockX, kBlockY);
+  if (g.dim == 2 && g.order == 2)
+    adjoint_step_kernel<2, 2><<<grid, block, 0, s>>>(g, zcur, zprev_next, c2, clam, wn, wprev, gam, kap, gf, gc);
+  else if (g.dim == 2)
+    adjoint_step_kernel<2, 4><<<grid, block, 0, s>>>(g, zcur, zprev_next, c2, clam, wn, wprev, gam, kap, gf, gc);
+  else if (g.order == 2)
+    adjoint_step_kernel<3, 2><<<grid, block, 0, s>>>(g, zcur, zprev_next, c2, clam, wn, wprev, gam, kap, gf, gc);
+  else
+    adjoint_step_kernel<3, 4><<<grid, block, 0, s>>>(g, zcur, zprev_next, c2, clam, wn, wprev, gam, kap, gf, gc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_first(const StepGeom &half, const double *z1, const double *z2, const double *c2,
+                                const double *clam, double w0, double *out, hipStream_t s) {
+  const dim3 grid = node_grid(half), block(kBlockX, kBlockY);
+  if (half.dim == 2 && half.order == 2)
+    adjoint_first_kernel<2, 2><<<grid, block, 0, s>>>(half, z1, z2, c2, clam, w0, out);
+  else if (half.dim == 2)
+    adjoint_first_kernel<2, 4><<<grid, block, 0, s>>>(half, z1, z2, c2, clam, w0, out);
+  else if (half.order == 2)
+    adjoint_first_kernel<3, 2><<<grid, block, 0, s>>>(half, z1, z2, c2, clam, w0, out);
+  else
+    adjoint_first_kernel<3, 4><<<grid, block, 0, s>>>(half, z1, z2, c2, clam, w0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_c2(const StepGeom &g, const double *c2, const double *in, double *out, bool divide,
+                           hipStream_t s) {
+  const dim3 grid = node_grid(g), block(kBlockX, kBlockY);
+  if (g.dim == 2) scale_c2_kernel<2><<<grid, block, 0, s>>>(g, c2, in, out, divide ? 1 : 0);
+  else scale_c2_kernel<3><<<grid, block, 0, s>>>(g, c2, in, out, divide ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_misfit(const double *u, const int64_t *idx, const double *data, int nrec, int64_t nodes,
+                         double *grad, double *out, hipStream_t s) {
+  misfit_kernel<<<1, kRedThreads, 0, s>>>(u, idx, data, nrec, nodes, grad, out);
+  return hipGetLastError();
+}
+
 }  // namespace wh

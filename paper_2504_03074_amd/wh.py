@@ -115,6 +115,11 @@ def _load():
         "wh_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
         "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
+        "wh_adjoint_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "wh_bind_adjoint_workspace": (st, [_vp, _vp, ctypes.c_size_t]),
+        "wh_gradient": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "wh_solve_adjoint": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, _vp, ctypes.POINTER(wh_solve_info)]),
+        "wh_receiver_misfit": (st, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _vp]),
         "wh_batch_create": (st, [ctypes.POINTER(_vp), ctypes.c_int32, _vp]),
         "wh_batch_destroy": (None, [_vp]),
         "wh_batch_last_error": (ctypes.c_char_p, [_vp]),
@@ -325,6 +330,36 @@ def wh_profile_read(ctx) -> wh_profile:
     out = wh_profile()
     _check(ctx, _load().wh_profile_read(ctx, ctypes.byref(out)))
     return out
+
+def wh_adjoint_workspace_size(ctx) -> int:
+    out = ctypes.c_size_t()
+    _check(ctx, _load().wh_adjoint_workspace_size(ctx, ctypes.byref(out)))
+    return out.value
+
+
+def wh_bind_adjoint_workspace(ctx, ptr, nbytes):
+    _check(ctx, _load().wh_bind_adjoint_workspace(ctx, _vp(ptr) if ptr else None, int(nbytes)))
+
+
+def wh_gradient(ctx, v: int, lam: int, grad_c2, grad_f, grad_v):
+    _check(ctx, _load().wh_gradient(ctx, _vp(v), _vp(lam), _vp(grad_c2) if grad_c2 else None,
+                                    _vp(grad_f) if grad_f else None, _vp(grad_v) if grad_v else None))
+
+
+def wh_solve_adjoint(ctx, opts: wh_solve_opts, g: int, lam: int) -> tuple[int, wh_solve_info]:
+    info = wh_solve_info()
+    st = _load().wh_solve_adjoint(ctx, ctypes.byref(opts), _vp(g), _vp(lam), ctypes.byref(info))
+    if st not in (WH_OK, WH_ENOTCONV):
+        _check(ctx, st)
+    return st, info
+
+
+def wh_receiver_misfit(ctx, u: int, idx: int, data: int, nrec: int, grad) -> float:
+    J = ctypes.c_double()
+    _check(ctx, _load().wh_receiver_misfit(ctx, _vp(u), _vp(idx) if idx else None, _vp(data) if data else None,
+                                           int(nrec), ctypes.byref(J), _vp(grad) if grad else None))
+    return J.value
+
 
 def _bcheck(batch, status):
     if status != WH_OK:
@@ -546,6 +581,50 @@ class Solver:
 
     def dot(self, x, y):
         return wh_dot(self.ctx, self._dev(x, "x"), self._dev(y, "y"))
+
+    # ---- discrete adjoint (FP64 state) ----
+    def _adjoint_ready(self):
+        need = wh_adjoint_workspace_size(self.ctx)
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < need:
+            self._adj_ws = self._torch.empty(need, dtype=self._torch.uint8, device=self.device)
+            wh_bind_adjoint_workspace(self.ctx, self._adj_ws.data_ptr(), need)
+
+    def gradient(self, v, lam, c2=True, f=True, v_grad=False):
+        """Sensitivities of lam . W_h(v, f) to c^2, f and v (dict of tensors)."""
+        self._adjoint_ready()
+        out = {}
+        if c2:
+            out["c2"] = self.new()
+        if f:
+            out["f"] = self.new()
+        if v_grad:
+            out["v"] = self.new()
+        p = lambda k: out[k].data_ptr() if k in out else None
+        wh_gradient(self.ctx, self._dev(v, "v"), self._dev(lam, "lam"), p("c2"), p("f"), p("v"))
+        return out
+
+    def solve_adjoint(self, g, method="cg", rtol=1e-8, maxit=1000, restart=None, lam0=None):
+        """lam with (I - S_h)^T lam = g (device tensor)."""
+        lam = self.new() if lam0 is None else lam0.clone()
+        opts, _ = make_opts(method, rtol, maxit, self.restart if restart is None else restart)
+        st, info = wh_solve_adjoint(self.ctx, opts, self._dev(g, "g"), self._dev(lam, "lam"))
+        d = info.as_dict()
+        d["converged"] = st == WH_OK
+        return lam, d
+
+    def receiver_misfit(self, u, idx, data, want_grad=True):
+        """(J, dJ/du) for flat receiver indices idx (int64 device tensor)."""
+        t = self._torch
+        if idx.dtype != t.int64 or idx.device != self.device or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 tensor on the solver's device")
+        if data.dtype != t.float64 or data.device != self.device or data.numel() != idx.numel():
+            raise ValueError("data must be a float64 tensor on the solver's device, one value per receiver")
+        data = data.contiguous()
+        g = self.new() if want_grad else None
+        J = wh_receiver_misfit(self.ctx, self._dev(u, "u"), idx.data_ptr(), data.data_ptr(), idx.numel(),
+                               g.data_ptr() if g is not None else None)
+        return J, g
 
     def profile_enable(self, enable=True):
         wh_profile_enable(self.ctx, enable)

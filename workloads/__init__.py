@@ -133,3 +133,43 @@ def batched_problems(count: int = 64, sizes=(256, 512, 1024), omega_range=(20.0,
 def materialise_source(dim: int, n: int, source) -> np.ndarray:
     center, bg, amp = source
     return _zero_walls(gaussian(dim, n, center, amp, bg))
+
+
+def ring_receivers(n: int, count: int = 128, inset: float = 0.05) -> np.ndarray:
+    """Flat node indices (2-D, x fastest) of `count` receivers evenly spaced
+    around the square ring `inset` inside the walls, starting at the corner
+    (inset, inset) and going counter-clockwise; positions snap to the nearest
+    node.  No random draws."""
+    per_side = count // 4
+    if per_side * 4 != count:
+        raise ValueError("count must be a multiple of 4")
+    a, b = inset, 1.0 - inset
+    t = a + (b - a) * np.arange(per_side) / per_side
+    xs = np.concatenate([t, np.full(per_side, b), b + a - t, np.full(per_side, a)])
+    ys = np.concatenate([np.full(per_side, a), t, np.full(per_side, b), b + a - t])
+    ix = np.rint(xs * n).astype(np.int64)
+    iy = np.rint(ys * n).astype(np.int64)
+    return iy * (n + 1) + ix
+
+
+def adjoint_problem(n: int = 1024, omega: float = 60.0, n_sources: int = 8, n_receivers: int = 128,
+                    seed: int = 5):
+    """Receiver-misfit gradient problem on the unit square, 2nd order:
+    background c^2 = 1; the 'true' model lowers c^2 by 0.2 in a Gaussian
+    bump 0.2 * exp(-|x - x_b|^2 / (2 * 0.1^2)) (so c_max stays 1 and both
+    models share the time step); n_sources Gaussian sources of amplitude 1
+    and width b_g = 400; receivers on the ring 0.05 inside the walls.
+
+    Draw order: bump centre x_b ~ U[0.35, 0.65]^2, then per source its
+    centre ~ U[0.2, 0.8]^2.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xb = rng.uniform(0.35, 0.65, 2)
+    centres = [tuple(rng.uniform(0.2, 0.8, 2)) for _ in range(n_sources)]
+    x, y = node_coords(2, n)
+    bump = 0.2 * np.exp(-((x - xb[0]) ** 2 + (y - xb[1]) ** 2) / (2.0 * 0.1 ** 2))
+    c2_bg = np.ones((n + 1, n + 1))
+    c2_true = c2_bg - bump
+    sources = [_zero_walls(gaussian(2, n, c, 1.0, 400.0)) for c in centres]
+    return dict(n=n, order=2, omega=omega, periods=1, cfl=0.9, c2_background=c2_bg, c2_true=c2_true,
+                sources=sources, receivers=ring_receivers(n, n_receivers), bump_centre=tuple(xb))
