@@ -26,6 +26,10 @@ Other modes (used to produce the committed rocprofv3 summaries):
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
                   by the batched CG, against solving them one at a time
+  --mode adjoint  receiver-misfit gradient on 1024^2 (omega = 60, 8 sources,
+                  128 receivers on a ring, data from a slower inclusion):
+                  forward solve, adjoint solve and checkpointed reverse sweep
+                  per source, against the plain forward solves
 """
 import argparse
 import json
@@ -56,7 +60,7 @@ def parse():
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint"], default="solve")
     ap.add_argument("--count", type=int, default=64, help="problems in --mode batch")
     ap.add_argument("--no-sequential", dest="sequential", action="store_false", default=True,
                     help="--mode batch: skip the one-at-a-time comparison")
@@ -231,6 +235,113 @@ def run_batch(args, dev):
     print(json.dumps(result), flush=True)
 
 
+def run_adjoint(args, dev):
+    """Gradient of J(c^2, f) = 1/2 sum_s ||R v*_s - d_s||^2 with respect to
+    c^2 and every source: per source a forward solve, the receiver misfit,
+    the adjoint solve (I - S)^T lam = R^T (R v* - d) and the checkpointed
+    reverse sweep, all to the same residual as the forward solves."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+
+    n = 1024 if args.n == 2048 else args.n
+    w = wl.adjoint_problem(n=n)
+    nsrc = len(w["sources"])
+    idx = torch.from_numpy(w["receivers"]).to(dev)
+    s = Solver(2, (n, n), order=w["order"], restart=2)
+    s.set_c2(w["c2_true"])
+    tp = s.set_frequency(w["omega"], periods=w["periods"], cfl_frac=w["cfl"])
+    nt = tp["nt"]
+    log(f"adjoint workload {n}^2, omega {w['omega']}, nt {nt}, {nsrc} sources, {idx.numel()} receivers")
+    data = []
+    for f in w["sources"]:  # observations from the true model (untimed)
+        s.set_source(f)
+        u, inf = s.solve(method="cg", rtol=args.rtol * 1e-2, maxit=args.maxit)
+        data.append(u.reshape(-1)[idx].clone())
+    s.set_c2(w["c2_background"])
+    s.set_frequency(w["omega"], periods=w["periods"], nt=nt)
+    sources = [torch.from_numpy(f).to(dev) for f in w["sources"]]
+    unknowns = (n - 1) ** 2
+    pts_apply = unknowns * nt * w["periods"]
+
+    def forward_only():
+        applies = 0
+        for f in sources:
+            s.set_source(f)
+            _, inf = s.solve(method="cg", rtol=args.rtol, maxit=args.maxit)
+            applies += inf["applies"]
+        return applies
+
+    def gradient():
+        J = 0.0
+        g_c2 = torch.zeros_like(sources[0])
+        g_f = []
+        applies = 0
+        for f, d in zip(sources, data):
+            s.set_source(f)
+            v, inf = s.solve(method="cg", rtol=args.rtol, maxit=args.maxit)
+            Js, gv = s.receiver_misfit(v, idx, d)
+            lam, ainf = s.solve_adjoint(gv, method="cg", rtol=args.rtol, maxit=args.maxit)
+            gr = s.gradient(v, lam, c2=True, f=True)
+            g_c2 += gr["c2"]
+            g_f.append(gr["f"])
+            J += Js
+            applies += inf["applies"] + ainf["applies"]
+        return J, g_c2, g_f, applies
+
+    for i in range(args.warmup):
+        log(f"warmup gradient {i + 1}/{args.warmup}")
+        gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        J, g_c2, g_f, applies = gradient()
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    # one reverse sweep per source: a forward sweep for the checkpoints, the
+    # recomputed segments (about one more) and the reverse steps
+    sweep_pts = nsrc * 3 * pts_apply
+    value = (applies * pts_apply + sweep_pts) / elapsed / 1e9
+    log(f"gradient: J = {J:.6e}, {elapsed:.2f}s, {applies} applies")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fapplies = forward_only()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    log(f"forward solves only: {tf:.2f}s, {fapplies} applies")
+    gm = g_c2.reshape(n + 1, n + 1)
+    peak = np.unravel_index(int(torch.argmax(gm.abs()).item()), gm.shape)
+    result = {
+        "metric": "grid-pt updates/s (GPts/s, % HBM roofline) + time to Helmholtz residual 1e-8",
+        "value": round(value, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded sources and inclusion; observations from the true model)",
+        "config": {
+            "workload": f"receiver-misfit gradient, {n}^2, 2nd order, omega={w['omega']}, {nsrc} Gaussian sources, "
+                        f"{idx.numel()} ring receivers, CG forward and adjoint solves to {args.rtol:g}",
+            "n": n, "nt": nt, "sources": nsrc, "receivers": int(idx.numel()), "rtol": args.rtol,
+        },
+        "time_to_gradient_s": round(elapsed, 4),
+        "forward_solves_s": round(tf, 4),
+        "gradient_over_forward": round(elapsed / tf, 3),
+        "misfit": J,
+        "grad_c2_norm": float(g_c2.norm()),
+        "grad_c2_peak_at": [int(peak[1]) / n, int(peak[0]) / n],
+        "inclusion_centre": list(w["bump_centre"]),
+        "applies": applies,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -268,6 +379,9 @@ def main():
 
     if args.mode == "batch":
         run_batch(args, dev)
+        return
+    if args.mode == "adjoint":
+        run_adjoint(args, dev)
         return
 
     order = 4
