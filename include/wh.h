@@ -330,6 +330,41 @@ WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
 WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
 
 /* ------------------------------------------------------------------------
+ * Deflation (Alg. 3, Sec. 5.2) with the eigenmodes of the unit box.
+ *
+ * With constant c^2 the eigenfunctions of L_h are the sine modes
+ * phi_k(x) = prod_a sqrt(2/n_a) sin(k_a pi x_a) (k_a = 1..n_a-1, orthonormal in
+ * the nodal sum) with the discrete eigenvalues lambda_k^2 of the order-p
+ * operator (App. B).  When deflation is set, wh_solve (FPI, GMRES and CG)
+ * removes the components along the deflated modes from the right-hand side,
+ * the initial guess and every operator output, iterates on the remaining
+ * modes (whose rate is max |beta_d| over the modes kept: the theorem on
+ * deflated convergence), and finally adds back (f, phi) / (omega^2 -
+ * lambda^2) phi for each deflated mode, so that the result is the discrete
+ * Helmholtz solution.  info->mu_pred is the deflated rate.  Deflation is
+ * cleared by any change of c^2 or the grid; wh_solve_rhs and the solvers
+ * built on it reject a context with deflation set.
+ * ---------------------------------------------------------------------- */
+#define WH_MAX_DEFLATION 1024
+
+/* The `count` modes with the largest |beta_d| (the slowest to converge) for
+ * the current grid, c^2 (constant) and frequency: modes (host, count x dim
+ * wave numbers k_x, k_y[, k_z]) and, nullable, the predicted rate over the
+ * remaining modes.  Grids with more than 2^24 modes are rejected. */
+WH_API wh_status wh_select_deflation(wh_ctx *ctx, int32_t count, int32_t *modes, double *mu_after);
+
+/* Bytes of caller-owned device workspace for `count` deflated modes (sine
+ * tables, eigenvalues, reduction partials). */
+WH_API wh_status wh_deflation_workspace_size(wh_ctx *ctx, int32_t count, size_t *bytes);
+
+/* Deflate the given modes (host array, count x dim; distinct, 1 <= k_a <=
+ * n_a - 1) in subsequent wh_solve calls, using `workspace` (256-byte aligned
+ * device memory of wh_deflation_workspace_size bytes, owned by the caller,
+ * kept until deflation is cleared).  count = 0 clears deflation.  Needs a
+ * constant c^2 (WH_EINVAL otherwise). */
+WH_API wh_status wh_set_deflation(wh_ctx *ctx, const int32_t *modes, int32_t count, void *workspace, size_t bytes);
+
+/* ------------------------------------------------------------------------
  * Discrete adjoint (FP64-state contexts).
  *
  * One application Y = W_h(v, f) (the explicit scheme of Sec. 4.2.1 and the

@@ -49,6 +49,12 @@ struct wh_ctx {
   int kernel = WH_KERNEL_AUTO, kblock = 0, tile = 0;
   char *adj = nullptr;  // adjoint workspace (checkpoints, reverse sweep)
   size_t adj_bytes = 0;
+  // deflation with sine modes (count 0 = off)
+  int defl_count = 0;
+  std::vector<int32_t> defl_modes;  // count x dim wave numbers
+  std::vector<double> defl_lam2;    // eigenvalue of -L_h per mode
+  double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr;
+  double *d_coef = nullptr, *d_coef_f = nullptr, *d_scale = nullptr, *d_dpart = nullptr;
   double *pinned = nullptr;  // host staging for reduction results
   size_t pinned_count = 0;
 
@@ -394,36 +400,63 @@ double sincd(double z, double T, double dt) {
   return std::sin(z * T) / (T * t / (0.5 * dt));
 }
 
+// Eigenvalue of -d^2/dx^2 (order p, Dirichlet) on sin(k pi x) with n cells:
+// n^2 sum_{mu < p/2} b_mu (4 sin^2(k pi / (2n)))^{mu+1}, b_0 = 1, b_1 = 1/12
+// (App. B).
+double axis_eigenvalue(int order, int64_t n, int64_t k) {
+  const double nn = (double)n;
+  const double s = std::sin(0.5 * M_PI * (double)k / nn);
+  const double s2 = s * s;
+  double lam = 4.0 * nn * nn * s2;
+  if (order == 4) lam += (4.0 / 3.0) * nn * nn * s2 * s2;
+  return lam;
+}
+
+// beta_d of the discrete filter (three-sinc form, App. A.3) for a mode whose
+// eigenvalue of -L_h is lam2; NaN if the mode is beyond the stability limit.
+double mode_beta(const wh_ctx *c, double lam2) {
+  const double dt = c->tp.dt, we = c->tp.omega_e, al = c->tp.alpha;
+  const double Tbar = (double)c->tp.nt * c->tp.periods * dt;
+  const double arg = 0.5 * std::sqrt(lam2) * dt;
+  if (arg >= 1.0) return NAN;
+  const double lt = (2.0 / dt) * std::asin(arg);
+  return sincd(we + lt, Tbar, dt) + sincd(we - lt, Tbar, dt) - al * sincd(lt, Tbar, dt);
+}
+
+int64_t mode_index(const wh_ctx *c, const int32_t *k) {
+  int64_t idx = 0, stride = 1;
+  for (int m = 0; m < c->dim; ++m) {
+    idx += (int64_t)(k[m] - 1) * stride;
+    stride *= c->n[m] - 1;
+  }
+  return idx;
+}
+
+// Theorem 2 (and, with deflation, the theorem on deflated convergence):
+// max |beta_d| over the sine modes that are not deflated (constant c^2).
 double predicted_rate(const wh_ctx *c) {
   if (!c->c2_is_const) return NAN;
   double modes = 1.0;
   for (int m = 0; m < c->dim; ++m) modes *= (double)(c->n[m] - 1);
   if (modes > (double)(1 << 22)) return NAN;
-  const double dt = c->tp.dt, we = c->tp.omega_e, al = c->tp.alpha;
-  const double Tbar = (double)c->tp.nt * c->tp.periods * dt;
   std::vector<double> ax[3];
-  for (int m = 0; m < c->dim; ++m) {
-    const double nn = (double)c->n[m];
-    for (int64_t k = 1; k < c->n[m]; ++k) {
-      const double s = std::sin(0.5 * M_PI * (double)k / nn);
-      const double s2 = s * s;
-      // eigenvalue of -d^2/dx^2 on sin(k pi x): 4 n^2 s^2 (p = 2), plus (4/3) n^2 s^4 (p = 4)
-      double lam = 4.0 * nn * nn * s2;
-      if (c->order == 4) lam += (4.0 / 3.0) * nn * nn * s2 * s2;
-      ax[m].push_back(lam);
-    }
+  for (int m = 0; m < c->dim; ++m)
+    for (int64_t k = 1; k < c->n[m]; ++k) ax[m].push_back(axis_eigenvalue(c->order, c->n[m], k));
+  std::vector<char> skip;
+  if (c->defl_count > 0) {
+    skip.assign((size_t)modes, 0);
+    for (int q = 0; q < c->defl_count; ++q) skip[(size_t)mode_index(c, &c->defl_modes[(size_t)q * c->dim])] = 1;
   }
   double mu = 0.0;
   const size_t nz = c->dim == 3 ? ax[2].size() : 1;
+  size_t idx = 0;
   for (size_t kz = 0; kz < nz; ++kz)
     for (double ly : ax[1])
       for (double lx : ax[0]) {
-        const double lam2 = c->c2_value * (lx + ly + (c->dim == 3 ? ax[2][kz] : 0.0));
-        const double arg = 0.5 * std::sqrt(lam2) * dt;
-        if (arg >= 1.0) continue;
-        const double lt = (2.0 / dt) * std::asin(arg);
-        const double b = sincd(we + lt, Tbar, dt) + sincd(we - lt, Tbar, dt) - al * sincd(lt, Tbar, dt);
-        mu = std::max(mu, std::fabs(b));
+        const size_t here = idx++;
+        if (!skip.empty() && skip[here]) continue;
+        const double b = mode_beta(c, c->c2_value * (lx + ly + (c->dim == 3 ? ax[2][kz] : 0.0)));
+        if (std::isfinite(b)) mu = std::max(mu, std::fabs(b));
       }
   return mu;
 }
@@ -577,6 +610,9 @@ wh_status wh_set_grid(wh_ctx *c, int32_t dim, const int64_t n[3], int32_t order,
   c->c2_is_const = false;
   c->kernel = WH_KERNEL_AUTO;
   c->kblock = c->tile = 0;
+  c->adj = nullptr;
+  c->adj_bytes = 0;
+  c->defl_count = 0;
   c->err.clear();
   return WH_OK;
 }
@@ -618,8 +654,10 @@ wh_status wh_bind_workspace(wh_ctx *c, void *ptr, size_t bytes, int32_t restart)
 }
 
 static wh_status finish_c2(wh_ctx *c) {
-  // Any change of c^2 invalidates the time parameters.
+  // Any change of c^2 invalidates the time parameters and the deflation
+  // eigenvalues.
   c->freq_set = false;
+  c->defl_count = 0;
   c->c2_set = true;
   return WH_OK;
 }
@@ -873,6 +911,37 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
 // solvers
 // ---------------------------------------------------------------------------
 // c->b <- the right-hand side: the given device vector, or b = W_h(0, f).
+// Deflation (Alg. 3): remove the components along the deflated sine modes,
+// or add back their Helmholtz components (f, phi) / (omega^2 - lambda^2).
+static wh_status defl_project(wh_ctx *c, double *x) {
+  if (c->defl_count == 0) return WH_OK;
+  const wh::StepGeom g = geometry(c, 1.0);
+  WH_HIP(c, wh::launch_mode_dot(g, false, x, c->defl_count, c->d_sx, c->d_sy, c->d_sz, c->d_dpart, c->d_coef,
+                                c->stream));
+  WH_HIP(c, wh::launch_mode_combine(g, x, c->defl_count, c->d_sx, c->d_sy, c->d_sz, c->d_coef, nullptr, -1.0,
+                                    c->stream));
+  return WH_OK;
+}
+
+static wh_status defl_inflate(wh_ctx *c, double *x) {
+  if (c->defl_count == 0) return WH_OK;
+  const double w2 = c->tp.omega * c->tp.omega;
+  std::vector<double> scale((size_t)c->defl_count);
+  for (int q = 0; q < c->defl_count; ++q) {
+    const double d = w2 - c->defl_lam2[(size_t)q];
+    if (d == 0.0) return fail(c, WH_EINVAL, "deflated mode %d is resonant (lambda = omega)", q);
+    scale[(size_t)q] = 1.0 / d;
+  }
+  WH_HIP(c, hipMemcpyAsync(c->d_scale, scale.data(), scale.size() * 8, hipMemcpyHostToDevice, c->stream));
+  const wh::StepGeom g = geometry(c, 1.0);
+  WH_HIP(c, wh::launch_mode_dot(g, c->prec == WH_FP32_STATE, c->f, c->defl_count, c->d_sx, c->d_sy, c->d_sz,
+                                c->d_dpart, c->d_coef_f, c->stream));
+  WH_HIP(c, wh::launch_mode_combine(g, x, c->defl_count, c->d_sx, c->d_sy, c->d_sz, c->d_coef_f, c->d_scale, 1.0,
+                                    c->stream));
+  WH_HIP(c, hipStreamSynchronize(c->stream));  // scale is a host temporary
+  return WH_OK;
+}
+
 static wh_status make_rhs(wh_ctx *c, const double *rhs, int *applies) {
   if (rhs) {
     if (rhs != c->b)
@@ -882,11 +951,12 @@ static wh_status make_rhs(wh_ctx *c, const double *rhs, int *applies) {
   WH_HIP(c, wh::launch_fill(c->tmp, 0.0, c->nodes, c->stream));
   WH_TRY(apply_impl(c, c->tmp, true, wh::FINAL_FILTER, c->b, nullptr));
   ++*applies;
-  return WH_OK;
+  return defl_project(c, c->b);
 }
 
 static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solve_info *info, const double *rhs) {
   const int nb = wh::reduction_blocks(c->nodes);
+  WH_TRY(defl_project(c, v));
   // ||b||: b = W_h(0, f); when the initial guess is zero the first iterate is b
   double vv;
   WH_TRY(dot_dev(c, v, v, 0));
@@ -908,8 +978,9 @@ static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solv
     if (rhs) {  // v <- S v + b
       WH_TRY(apply_impl(c, v, false, wh::FINAL_FILTER, c->tmp, nullptr));
       WH_HIP(c, wh::launch_add(c->tmp, c->b, c->tmp, c->nodes, c->stream));
-    } else {  // v <- W_h(v, f)
+    } else {  // v <- W_h(v, f), deflated
       WH_TRY(apply_impl(c, v, true, wh::FINAL_FILTER, c->tmp, nullptr));
+      WH_TRY(defl_project(c, c->tmp));
     }
     ++applies;
     WH_HIP(c, wh::launch_diff_norm_copy(c->tmp, v, c->nodes, c->partials, nb, c->stream));
@@ -930,6 +1001,7 @@ static wh_status solve_fpi(wh_ctx *c, const wh_solve_opts *o, double *v, wh_solv
     if (o->rtol > 0.0 && rel <= o->rtol) break;
   }
   if (k > o->maxit) k = o->maxit;
+  if (st == WH_OK) WH_TRY(defl_inflate(c, v));
   if (info) {
     info->iters = k;
     info->applies = applies;
@@ -973,9 +1045,11 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
   wh_status st = WH_OK;
   bool done = false;
   // r = b - A x into V_0
+  WH_TRY(defl_project(c, x));
   WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
   ++applies;
   WH_HIP(c, wh::launch_sub(c->b, c->tmp, Vj(0), N, c->stream));
+  WH_TRY(defl_project(c, Vj(0)));
   while (!done) {
     double rr;
     WH_TRY(dot_dev(c, Vj(0), Vj(0), S_NRM));
@@ -995,6 +1069,7 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
     for (int j = 0; j < m && total < o->maxit; ++j) {
       double *w = Vj(j + 1);
       WH_TRY(apply_impl(c, Vj(j), false, wh::FINAL_A, w, nullptr));
+      WH_TRY(defl_project(c, w));
       ++applies;
       // classical Gram-Schmidt, twice (coefficients stay on the device between passes)
       WH_HIP(c, wh::launch_mdot(c->V, c->ldv, j + 1, w, N, c->partials, nb, c->stream));
@@ -1047,7 +1122,9 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
     WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
     ++applies;
     WH_HIP(c, wh::launch_sub(c->b, c->tmp, Vj(0), N, c->stream));
+    WH_TRY(defl_project(c, Vj(0)));
   }
+  if (st == WH_OK) WH_TRY(defl_inflate(c, x));
   WH_HIP(c, hipStreamSynchronize(c->stream));
   if (info) {
     info->iters = total;
@@ -1088,10 +1165,12 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
   if (!std::isfinite(bnorm)) return fail(c, WH_ENONFINITE, "||b|| is not finite");
 
   // r = b - A x, p = r, slot(k) = [<r,r>_w, <r,r>]
+  WH_TRY(defl_project(c, x));
   auto restart = [&](int64_t k, double *rel) -> wh_status {
     WH_TRY(apply_impl(c, x, false, wh::FINAL_A, c->tmp, nullptr));
     ++applies;
     WH_HIP(c, wh::launch_sub(c->b, c->tmp, r, N, c->stream));
+    WH_TRY(defl_project(c, r));
     WH_HIP(c, wh::launch_wdot(r, r, c2w, fp32, N, c->partials, nb, c->stream));
     WH_TRY(reduce_to(c, 1, slot(k)));
     WH_TRY(dot_dev(c, r, r, slot(k) + 1));
@@ -1109,6 +1188,7 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
   rel0 = rel;
   while (bnorm > 0.0 && rel > o->rtol && k < o->maxit) {
     WH_TRY(apply_impl(c, p, false, wh::FINAL_A, q, nullptr));  // q = A p
+    WH_TRY(defl_project(c, q));
     ++applies;
     WH_HIP(c, wh::launch_wdot(p, q, c2w, fp32, N, c->partials, nb, c->stream));
     WH_TRY(reduce_to(c, 1, S_PQ));
@@ -1139,6 +1219,7 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
     }
     WH_HIP(c, wh::launch_xpay(r, p, c->scal + nxt, c->scal + cur, N, c->stream));
   }
+  if (st == WH_OK) WH_TRY(defl_inflate(c, x));
   WH_HIP(c, hipStreamSynchronize(c->stream));
   if (info) {
     info->iters = (int32_t)k;
@@ -1173,6 +1254,9 @@ static wh_status solve_dispatch(wh_ctx *c, const wh_solve_opts *o, const double 
   if (rhs) {
     WH_TRY(check_dev(c, rhs, "b"));
     if (rhs == v) return fail(c, WH_EINVAL, "b may not alias v");
+    if (c->defl_count > 0)
+      return fail(c, WH_EINVAL, "deflation applies to wh_solve (right-hand side from the source); "
+                                "call wh_set_deflation with count 0 first");
   }
   if (info) std::memset(info, 0, sizeof *info);
   const auto t0 = std::chrono::steady_clock::now();
@@ -1290,6 +1374,149 @@ wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, con
     st = fail(hi, WH_ENOTCONV, "mixed-precision refinement reached maxit = %d at relative residual %g",
               outer->maxit, rel);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// deflation with the sine modes of the unit box (Alg. 3)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DeflLayout {
+  size_t sx, sy, sz, coef, coef_f, scale, part, total;
+  int nblocks;
+};
+
+DeflLayout defl_layout(const wh_ctx *c, int count) {
+  DeflLayout L{};
+  L.nblocks = wh::mode_blocks(geometry(c, 1.0));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t M = (size_t)count;
+  L.sx = take(M * (size_t)(c->n[0] + 1) * 8);
+  L.sy = take(M * (size_t)(c->n[1] + 1) * 8);
+  L.sz = take(c->dim == 3 ? M * (size_t)(c->n[2] + 1) * 8 : 8);
+  L.coef = take(M * 8);
+  L.coef_f = take(M * 8);
+  L.scale = take(M * 8);
+  L.part = take(M * (size_t)L.nblocks * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+wh_status wh_deflation_workspace_size(wh_ctx *c, int32_t count, size_t *bytes) {
+  WH_TRY(need(c, true, false, false, false, false));
+  if (!bytes) return fail(c, WH_EINVAL, "bytes is NULL");
+  if (count < 0 || count > WH_MAX_DEFLATION) return fail(c, WH_EINVAL, "count must be in 0..%d", WH_MAX_DEFLATION);
+  *bytes = defl_layout(c, count).total;
+  return WH_OK;
+}
+
+wh_status wh_set_deflation(wh_ctx *c, const int32_t *modes, int32_t count, void *workspace, size_t bytes) {
+  WH_TRY(need(c, true, true, true, false, false));
+  if (count == 0) {
+    c->defl_count = 0;
+    return WH_OK;
+  }
+  if (!c->c2_is_const) return fail(c, WH_EINVAL, "deflation with sine modes needs a constant c^2");
+  if (count < 0 || count > WH_MAX_DEFLATION) return fail(c, WH_EINVAL, "count must be in 0..%d", WH_MAX_DEFLATION);
+  if (!modes) return fail(c, WH_EINVAL, "modes is NULL");
+  const DeflLayout L = defl_layout(c, count);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(c, WH_EINVAL, "deflation workspace must be a 256-byte aligned device pointer");
+  if (bytes < L.total) return fail(c, WH_ENOMEM, "deflation workspace of %zu bytes needed", L.total);
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, workspace, "deflation workspace"));
+  std::vector<int64_t> seen;
+  seen.reserve((size_t)count);
+  for (int q = 0; q < count; ++q) {
+    for (int m = 0; m < c->dim; ++m) {
+      const int32_t k = modes[(size_t)q * c->dim + m];
+      if (k < 1 || k >= c->n[m]) return fail(c, WH_EINVAL, "mode %d: wave number %d outside 1..%lld", q, k,
+                                              (long long)(c->n[m] - 1));
+    }
+    seen.push_back(mode_index(c, modes + (size_t)q * c->dim));
+  }
+  std::sort(seen.begin(), seen.end());
+  if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return fail(c, WH_EINVAL, "modes repeat");
+  char *base = static_cast<char *>(workspace);
+  c->d_sx = reinterpret_cast<double *>(base + L.sx);
+  c->d_sy = reinterpret_cast<double *>(base + L.sy);
+  c->d_sz = reinterpret_cast<double *>(base + L.sz);
+  c->d_coef = reinterpret_cast<double *>(base + L.coef);
+  c->d_coef_f = reinterpret_cast<double *>(base + L.coef_f);
+  c->d_scale = reinterpret_cast<double *>(base + L.scale);
+  c->d_dpart = reinterpret_cast<double *>(base + L.part);
+  // normalized 1-D factors sqrt(2/n) sin(k pi i / n), exactly 0 on the walls
+  double *tables[3] = {c->d_sx, c->d_sy, c->d_sz};
+  c->defl_lam2.assign((size_t)count, 0.0);
+  for (int m = 0; m < c->dim; ++m) {
+    const int64_t n = c->n[m];
+    std::vector<double> t((size_t)count * (n + 1), 0.0);
+    const double nrm = std::sqrt(2.0 / (double)n);
+    for (int q = 0; q < count; ++q) {
+      const int32_t k = modes[(size_t)q * c->dim + m];
+      for (int64_t i = 1; i < n; ++i) t[(size_t)q * (n + 1) + i] = nrm * std::sin(M_PI * (double)k * (double)i / (double)n);
+      c->defl_lam2[(size_t)q] += c->c2_value * axis_eigenvalue(c->order, n, k);
+    }
+    WH_HIP(c, hipMemcpyAsync(tables[m], t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream));
+    WH_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  c->defl_modes.assign(modes, modes + (size_t)count * c->dim);
+  c->defl_count = count;
+  return WH_OK;
+}
+
+wh_status wh_select_deflation(wh_ctx *c, int32_t count, int32_t *modes, double *mu_after) {
+  WH_TRY(need(c, true, false, true, false, true));
+  if (!c->c2_is_const) return fail(c, WH_EINVAL, "deflation with sine modes needs a constant c^2");
+  if (count < 0 || count > WH_MAX_DEFLATION) return fail(c, WH_EINVAL, "count must be in 0..%d", WH_MAX_DEFLATION);
+  if (count > 0 && !modes) return fail(c, WH_EINVAL, "modes is NULL");
+  double total = 1.0;
+  for (int m = 0; m < c->dim; ++m) total *= (double)(c->n[m] - 1);
+  if (total > (double)(1 << 24)) return fail(c, WH_EINVAL, "too many modes to rank (%.0f)", total);
+  if ((double)count > total) return fail(c, WH_EINVAL, "count %d exceeds the %.0f modes", count, total);
+  std::vector<double> ax[3];
+  for (int m = 0; m < c->dim; ++m)
+    for (int64_t k = 1; k < c->n[m]; ++k) ax[m].push_back(axis_eigenvalue(c->order, c->n[m], k));
+  const size_t M = (size_t)total;
+  std::vector<double> absb(M);
+  const size_t nx = ax[0].size(), ny = ax[1].size();
+  for (size_t idx = 0; idx < M; ++idx) {
+    const size_t i = idx % nx, j = (idx / nx) % ny, k = idx / (nx * ny);
+    const double lam2 = c->c2_value * (ax[0][i] + ax[1][j] + (c->dim == 3 ? ax[2][k] : 0.0));
+    const double b = mode_beta(c, lam2);
+    absb[idx] = std::isfinite(b) ? std::fabs(b) : 0.0;
+  }
+  // the count slowest-converging modes (largest |beta_d|; ties by index)
+  std::vector<int64_t> order(M);
+  for (size_t i = 0; i < M; ++i) order[i] = (int64_t)i;
+  auto slower = [&](int64_t a, int64_t b) { return absb[a] > absb[b] || (absb[a] == absb[b] && a < b); };
+  std::partial_sort(order.begin(), order.begin() + count, order.end(), slower);
+  for (int q = 0; q < count; ++q) {
+    const size_t idx = (size_t)order[(size_t)q];
+    modes[(size_t)q * c->dim + 0] = (int32_t)(idx % nx) + 1;
+    modes[(size_t)q * c->dim + 1] = (int32_t)((idx / nx) % ny) + 1;
+    if (c->dim == 3) modes[(size_t)q * c->dim + 2] = (int32_t)(idx / (nx * ny)) + 1;
+  }
+  if (mu_after) {
+    std::vector<char> taken(M, 0);
+    for (int q = 0; q < count; ++q) taken[(size_t)order[(size_t)q]] = 1;
+    double mu = 0.0;
+    for (size_t idx = 0; idx < M; ++idx)
+      if (!taken[idx]) mu = std::max(mu, absb[idx]);
+    *mu_after = mu;
+  }
+  return WH_OK;
 }
 
 }  // extern "C"

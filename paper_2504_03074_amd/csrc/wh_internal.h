@@ -187,6 +187,15 @@ hipError_t launch_adjoint_first(const StepGeom &half, const double *z1, const do
 // out = in * c2 or in / c2 (divide) on interior nodes, 0 on walls
 hipError_t launch_scale_c2(const StepGeom &g, const double *c2, const double *in, double *out, bool divide,
                            hipStream_t s);
+// Deflation with sine modes: mode_blocks = work-groups (and partials per
+// mode) of the mode kernels; coef[m] = sum_interior v phi_m (v in state
+// precision when fp32); out += alpha coef[m] scale[m] phi_m (scale nullable).
+int mode_blocks(const StepGeom &g);
+hipError_t launch_mode_dot(const StepGeom &g, bool fp32, const void *v, int nmodes, const double *sx, const double *sy,
+                           const double *sz, double *partials, double *coef, hipStream_t s);
+hipError_t launch_mode_combine(const StepGeom &g, double *out, int nmodes, const double *sx, const double *sy,
+                               const double *sz, const double *coef, const double *scale, double alpha,
+                               hipStream_t s);
 // receiver misfit: out[0] = J, out[1] = count of out-of-range indices;
 // grad (nullable, pre-zeroed) += residuals at the receiver nodes
 hipError_t launch_misfit(const double *u, const int64_t *idx, const double *data, int nrec, int64_t nodes,

@@ -1018,4 +1018,178 @@ hipError_t launch_misfit(const double *u, const int64_t *idx, const double *data
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// deflation with the sine modes of the unit box (Alg. 3)
+//
+// A mode is phi_m(i, j, k) = sx[m][i] sy[m][j] sz[m][k] (tables of the
+// normalized 1-D sine factors, exactly 0 on the walls).  A work-group covers
+// a 64 x kDefRows tile of (x, y) and every z plane; modes are taken kDefChunk
+// at a time with their factors for the tile staged in LDS.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kDefChunk = 32;
+constexpr int kDefRows = 8;
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void mode_dot_kernel(StepGeom g, const T *__restrict__ v, int nmodes,
+                                                       const double *__restrict__ sx, const double *__restrict__ sy,
+                                                       const double *__restrict__ sz, double *__restrict__ partials,
+                                                       int nblocks) {
+  __shared__ double tx[kDefChunk][64];
+  __shared__ double ty[kDefChunk][kDefRows];
+  __shared__ double red[4][kDefChunk];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int j0 = blockIdx.y * kDefRows;
+  const int b = blockIdx.x + blockIdx.y * gridDim.x;
+  const int nzp = DIM == 3 ? g.nz + 1 : 1;
+  for (int m0 = 0; m0 < nmodes; m0 += kDefChunk) {
+    const int mc = min(kDefChunk, nmodes - m0);
+    for (int t = threadIdx.x; t < kDefChunk * 64; t += 256) {
+      const int q = t / 64, l = t % 64, ii = blockIdx.x * 64 + l;
+      tx[q][l] = (q < mc && ii <= g.nx) ? sx[(int64_t)(m0 + q) * (g.nx + 1) + ii] : 0.0;
+    }
+    for (int t = threadIdx.x; t < kDefChunk * kDefRows; t += 256) {
+      const int q = t / kDefRows, r = t % kDefRows, jj = j0 + r;
+      ty[q][r] = (q < mc && jj <= g.ny) ? sy[(int64_t)(m0 + q) * (g.ny + 1) + jj] : 0.0;
+    }
+    __syncthreads();
+    double acc[kDefChunk];
+#pragma unroll
+    for (int q = 0; q < kDefChunk; ++q) acc[q] = 0.0;
+    const bool col = i > 0 && i < g.nx;
+    for (int k = (DIM == 3 ? 1 : 0); k < (DIM == 3 ? g.nz : 1); ++k) {
+      for (int r = wave; r < kDefRows; r += 4) {
+        const int j = j0 + r;
+        if (!col || j <= 0 || j >= g.ny) continue;
+        const double val = static_cast<double>(v[(int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz]);
+#pragma unroll
+        for (int q = 0; q < kDefChunk; ++q) {
+          double w = tx[q][lane] * ty[q][r];
+          if (DIM == 3) w *= (q < mc) ? sz[(int64_t)(m0 + q) * (g.nz + 1) + k] : 0.0;
+          acc[q] += val * w;
+        }
+      }
+    }
+    (void)nzp;
+#pragma unroll
+    for (int q = 0; q < kDefChunk; ++q) {
+      const double sum = wave_sum(acc[q]);
+      if (lane == 0) red[wave][q] = sum;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < mc) {
+      const int q = threadIdx.x;
+      partials[(int64_t)(m0 + q) * nblocks + b] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
+    __syncthreads();
+  }
+}
+
+// coef[m] = sum of the mode's partials (one work-group per mode)
+__global__ __launch_bounds__(kRedThreads) void mode_reduce_kernel(const double *__restrict__ partials, int nblocks,
+                                                                  double *__restrict__ coef) {
+  __shared__ double sm[4];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += partials[(int64_t)blockIdx.x * nblocks + b];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) coef[blockIdx.x] = s;
+}
+
+// out += sum_m alpha coef[m] (scale[m]) phi_m on interior nodes
+template <int DIM>
+__global__ __launch_bounds__(256) void mode_combine_kernel(StepGeom g, double *__restrict__ out, int nmodes,
+                                                           const double *__restrict__ sx,
+                                                           const double *__restrict__ sy,
+                                                           const double *__restrict__ sz,
+                                                           const double *__restrict__ coef,
+                                                           const double *__restrict__ scale, double alpha) {
+  __shared__ double tx[kDefChunk][64];
+  __shared__ double ty[kDefChunk][kDefRows];
+  __shared__ double am[kDefChunk];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int j0 = blockIdx.y * kDefRows;
+  const bool col = i > 0 && i < g.nx;
+  for (int m0 = 0; m0 < nmodes; m0 += kDefChunk) {
+    const int mc = min(kDefChunk, nmodes - m0);
+    for (int t = threadIdx.x; t < kDefChunk * 64; t += 256) {
+      const int q = t / 64, l = t % 64, ii = blockIdx.x * 64 + l;
+      tx[q][l] = (q < mc && ii <= g.nx) ? sx[(int64_t)(m0 + q) * (g.nx + 1) + ii] : 0.0;
+    }
+    for (int t = threadIdx.x; t < kDefChunk * kDefRows; t += 256) {
+      const int q = t / kDefRows, r = t % kDefRows, jj = j0 + r;
+      ty[q][r] = (q < mc && jj <= g.ny) ? sy[(int64_t)(m0 + q) * (g.ny + 1) + jj] : 0.0;
+    }
+    if ((int)threadIdx.x < kDefChunk) {
+      const int q = threadIdx.x;
+      am[q] = q < mc ? alpha * coef[m0 + q] * (scale ? scale[m0 + q] : 1.0) : 0.0;
+    }
+    __syncthreads();
+    for (int k = (DIM == 3 ? 1 : 0); k < (DIM == 3 ? g.nz : 1); ++k) {
+      for (int r = wave; r < kDefRows; r += 4) {
+        const int j = j0 + r;
+        if (!col || j <= 0 || j >= g.ny) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kDefChunk; ++q) {
+          double w = am[q] * tx[q][lane] * ty[q][r];
+          if (DIM == 3) w *= (q < mc) ? sz[(int64_t)(m0 + q) * (g.nz + 1) + k] : 0.0;
+          s += w;
+        }
+        out[(int64_t)i + (int64_t)j * g.sy + (int64_t)k * g.sz] += s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+dim3 mode_grid(const StepGeom &g) {
+  return dim3((unsigned)((g.nx + 1 + 63) / 64), (unsigned)((g.ny + 1 + kDefRows - 1) / kDefRows), 1);
+}
+
+}  // namespace
+
+int mode_blocks(const StepGeom &g) {
+  const dim3 d = mode_grid(g);
+  return (int)(d.x * d.y);
+}
+
+hipError_t launch_mode_dot(const StepGeom &g, bool fp32, const void *v, int nmodes, const double *sx, const double *sy,
+                           const double *sz, double *partials, double *coef, hipStream_t s) {
+  if (nmodes <= 0) return hipSuccess;
+  const dim3 grid = mode_grid(g);
+  const int nb = (int)(grid.x * grid.y);
+  if (g.dim == 2) {
+    if (fp32)
+      mode_dot_kernel<float, 2><<<grid, 256, 0, s>>>(g, static_cast<const float *>(v), nmodes, sx, sy, sz, partials,
+                                                     nb);
+    else
+      mode_dot_kernel<double, 2><<<grid, 256, 0, s>>>(g, static_cast<const double *>(v), nmodes, sx, sy, sz, partials,
+                                                      nb);
+  } else {
+    if (fp32)
+      mode_dot_kernel<float, 3><<<grid, 256, 0, s>>>(g, static_cast<const float *>(v), nmodes, sx, sy, sz, partials,
+                                                     nb);
+    else
+      mode_dot_kernel<double, 3><<<grid, 256, 0, s>>>(g, static_cast<const double *>(v), nmodes, sx, sy, sz, partials,
+                                                      nb);
+  }
+  mode_reduce_kernel<<<nmodes, kRedThreads, 0, s>>>(partials, nb, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_combine(const StepGeom &g, double *out, int nmodes, const double *sx, const double *sy,
+                               const double *sz, const double *coef, const double *scale, double alpha,
+                               hipStream_t s) {
+  if (nmodes <= 0) return hipSuccess;
+  const dim3 grid = mode_grid(g);
+  if (g.dim == 2)
+    mode_combine_kernel<2><<<grid, 256, 0, s>>>(g, out, nmodes, sx, sy, sz, coef, scale, alpha);
+  else
+    mode_combine_kernel<3><<<grid, 256, 0, s>>>(g, out, nmodes, sx, sy, sz, coef, scale, alpha);
+  return hipGetLastError();
+}
+
 }  // namespace wh

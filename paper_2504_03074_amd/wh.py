@@ -115,6 +115,10 @@ def _load():
         "wh_autotune": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
         "wh_profile_read": (st, [_vp, ctypes.POINTER(wh_profile)]),
+        "wh_select_deflation": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double)]),
+        "wh_deflation_workspace_size": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+        "wh_set_deflation": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _vp, ctypes.c_size_t]),
         "wh_adjoint_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "wh_bind_adjoint_workspace": (st, [_vp, _vp, ctypes.c_size_t]),
         "wh_gradient": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -330,6 +334,27 @@ def wh_profile_read(ctx) -> wh_profile:
     out = wh_profile()
     _check(ctx, _load().wh_profile_read(ctx, ctypes.byref(out)))
     return out
+
+def wh_select_deflation(ctx, count: int, dim: int):
+    """(modes as a list of dim-tuples, predicted deflated rate)."""
+    arr = (ctypes.c_int32 * max(count * dim, 1))()
+    mu = ctypes.c_double()
+    _check(ctx, _load().wh_select_deflation(ctx, int(count), arr, ctypes.byref(mu)))
+    return [tuple(arr[q * dim + m] for m in range(dim)) for q in range(count)], mu.value
+
+
+def wh_deflation_workspace_size(ctx, count: int) -> int:
+    out = ctypes.c_size_t()
+    _check(ctx, _load().wh_deflation_workspace_size(ctx, int(count), ctypes.byref(out)))
+    return out.value
+
+
+def wh_set_deflation(ctx, modes, ptr, nbytes):
+    modes = list(modes)
+    dim = len(modes[0]) if modes else 1
+    arr = (ctypes.c_int32 * max(len(modes) * dim, 1))(*[int(k) for m in modes for k in m])
+    _check(ctx, _load().wh_set_deflation(ctx, arr, len(modes), _vp(ptr) if ptr else None, int(nbytes)))
+
 
 def wh_adjoint_workspace_size(ctx) -> int:
     out = ctypes.c_size_t()
@@ -581,6 +606,28 @@ class Solver:
 
     def dot(self, x, y):
         return wh_dot(self.ctx, self._dev(x, "x"), self._dev(y, "y"))
+
+    # ---- deflation (constant c^2) ----
+    def select_deflation(self, count):
+        """The `count` slowest-converging sine modes and the deflated rate."""
+        return wh_select_deflation(self.ctx, count, self.dim)
+
+    def set_deflation(self, modes=None, count=None):
+        """Deflate the given modes (list of wave-number tuples), or the
+        `count` slowest ones; returns (modes, predicted deflated rate or None).
+        modes=[] / count=0 clears deflation."""
+        mu = None
+        if modes is None:
+            modes, mu = self.select_deflation(int(count or 0))
+        modes = [tuple(int(k) for k in m) for m in modes]
+        if not modes:
+            wh_set_deflation(self.ctx, [], None, 0)
+            self._defl_ws = None
+            return [], mu
+        need = wh_deflation_workspace_size(self.ctx, len(modes))
+        self._defl_ws = self._torch.empty(need, dtype=self._torch.uint8, device=self.device)
+        wh_set_deflation(self.ctx, modes, self._defl_ws.data_ptr(), need)
+        return modes, mu
 
     # ---- discrete adjoint (FP64 state) ----
     def _adjoint_ready(self):
