@@ -84,16 +84,18 @@ def measured_traffic(n, precision, tun):
     the workload differs from the one profiled or the kernel source changed
     since the counters were taken."""
     import hashlib
-    profiled = tun["kernel"] == "blocked_2d" and tun["kblock"] == 4 and tun["tile"] == 64
-    if not (n == 2048 and precision == "fp64" and profiled) or not os.path.exists(COUNTER_SUMMARY):
+    if not (n == 2048 and precision == "fp64" and tun["kernel"] == "blocked_2d") or not os.path.exists(COUNTER_SUMMARY):
         return None
+    keys = ("traffic_bytes_per_launch", "kernel_source_sha256", "kblock", "tile_rows")
     fields = {}
     for line in open(COUNTER_SUMMARY):
-        if "=" in line and line.split("=")[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if "=" in line and line.split("=")[0].strip() in keys:
             k, v = line.split("=", 1)
             fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != sha:
+        return None
+    if fields.get("kblock") != str(tun["kblock"]) or fields.get("tile_rows") != str(tun["tile"]):
         return None
     return float(fields["traffic_bytes_per_launch"])
 

@@ -280,6 +280,12 @@ wh_status drain_profile(wh_ctx *c) {
   return WH_OK;
 }
 
+// Leapfrog steps per blocked launch when the caller does not choose: the
+// fastest measured on MI355X at the default tile heights (2048^2, p = 4:
+// FP64 K = 5, FP32 K = 6; p = 2: K = 8 — more steps per HBM pass outweigh the
+// larger halo until the arithmetic dominates).
+int default_kblock(int order, bool fp32) { return order == 2 ? 8 : (fp32 ? 6 : 5); }
+
 struct Tuning {
   int kernel, kblock, tile;
 };
@@ -288,7 +294,7 @@ struct Tuning {
 Tuning resolve_tuning(const wh_ctx *c) {
   const bool fp32 = c->prec == WH_FP32_STATE;
   if (c->kernel == WH_KERNEL_AUTO) {
-    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, 4, wh::block_default_rows(fp32)};
+    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32)};
     return {WH_KERNEL_NODE, 1, 0};
   }
   if (c->kernel == WH_KERNEL_BLOCKED_2D)
@@ -850,7 +856,7 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
     for (int zb : {4, 8, 16}) cands.push_back({WH_KERNEL_ZCOL_3D, 1, zb});
   } else {
     for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
-      for (int rows : {32, 64, 128, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
+      for (int rows : {32, 64, 80, 128, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
   }
   const Tuning saved{c->kernel, c->kblock, c->tile};
   const bool saved_prof = c->profiling;
@@ -1778,7 +1784,7 @@ wh_status bfail(wh_batch *b, wh_status st, const char *fmt, ...) {
 
 void batch_resolve_tuning(wh_batch *b) {
   const bool fp32 = b->prec == WH_FP32_STATE;
-  if (b->K == 0) b->K = 4;
+  if (b->K == 0) b->K = default_kblock(b->order, fp32);
   if (b->rows == 0) b->rows = wh::block_default_rows(fp32);
 }
 
@@ -2066,7 +2072,7 @@ wh_status wh_batch_set_tuning(wh_batch *b, int32_t kblock, int32_t tile) {
   if (b->finalized) return bfail(b, WH_ESTATE, "batch already finalized");
   if (b->probs.empty()) return bfail(b, WH_ESTATE, "add problems first");
   const bool fp32 = b->prec == WH_FP32_STATE;
-  const int K = kblock == 0 ? 4 : kblock;
+  const int K = kblock == 0 ? default_kblock(b->order, fp32) : kblock;
   const int rows = tile == 0 ? wh::block_default_rows(fp32) : tile;
   if (K < 2 || !wh::block_config_supported(fp32, b->order, K, rows) || rows > 8 * (fp32 ? 24 : 8))
     return bfail(b, WH_EINVAL, "kblock %d / tile %d not supported for batches", kblock, tile);

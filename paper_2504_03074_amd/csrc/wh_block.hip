@@ -369,13 +369,22 @@ hipError_t dispatch_nw(const StepGeom &g, int nw, int ksteps, const void *ip, co
   switch (nw) {
     case 4: return launch_if_fits<T, P, K, 4>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     case 8: return launch_if_fits<T, P, K, 8>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    // FP32's 24-row arrays do not fit groups of more than 8 waves
+    case 10:
+      if constexpr (sizeof(T) == 8)
+        return launch_if_fits<T, P, K, 10>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      return hipErrorInvalidValue;
     case 16:
-      // FP32's 24-row arrays do not fit 1024-thread groups without spilling
       if constexpr (sizeof(T) == 8)
         return launch_if_fits<T, P, K, 16>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
+}
+
+// Steps per launch: 2..6 for p = 4 (halo 2K); 2, 3, 4, 6, 8 for p = 2 (halo K).
+constexpr bool k_instantiated(int P, int K) {
+  return P == 4 ? (K >= 2 && K <= 6) : (K == 2 || K == 3 || K == 4 || K == 6 || K == 8);
 }
 
 template <typename T, int P>
@@ -386,6 +395,15 @@ hipError_t dispatch_k(const StepGeom &g, int K, int nw, int ksteps, const void *
     case 2: return dispatch_nw<T, P, 2>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     case 3: return dispatch_nw<T, P, 3>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     case 4: return dispatch_nw<T, P, 4>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 5:
+      if constexpr (k_instantiated(P, 5))
+        return dispatch_nw<T, P, 5>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      return hipErrorInvalidValue;
+    case 6: return dispatch_nw<T, P, 6>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 8:
+      if constexpr (k_instantiated(P, 8))
+        return dispatch_nw<T, P, 8>(g, nw, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -393,12 +411,12 @@ hipError_t dispatch_k(const StepGeom &g, int K, int nw, int ksteps, const void *
 }  // namespace
 
 bool block_config_supported(bool fp32, int order, int K, int rows) {
-  if (!(order == 2 || order == 4) || K < 2 || K > kMaxBlockSteps) return false;
+  if (!(order == 2 || order == 4) || !k_instantiated(order, K)) return false;
   const int rs = fp32 ? RowsPerLane<float>::RS : RowsPerLane<double>::RS;
   if (rows % rs != 0) return false;
   const int nw = rows / rs;
-  if (nw != 4 && nw != 8 && !(nw == 16 && !fp32)) return false;
-  return rows - 2 * K * (order / 2) > 0;
+  if (nw != 4 && nw != 8 && !((nw == 10 || nw == 16) && !fp32)) return false;
+  return rows - 2 * K * (order / 2) > 0 && 64 - 2 * K * (order / 2) > 0;
 }
 
 int block_default_rows(bool fp32) { return fp32 ? 4 * RowsPerLane<float>::RS : 8 * RowsPerLane<double>::RS; }
@@ -460,6 +478,15 @@ hipError_t batch_k(int K, int nw, bool force, const BatchDesc *descs, const int 
     case 2: return batch_nw<T, P, 2>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
     case 3: return batch_nw<T, P, 3>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
     case 4: return batch_nw<T, P, 4>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    case 5:
+      if constexpr (k_instantiated(P, 5))
+        return batch_nw<T, P, 5>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+      return hipErrorInvalidValue;
+    case 6: return batch_nw<T, P, 6>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+    case 8:
+      if constexpr (k_instantiated(P, 8))
+        return batch_nw<T, P, 8>(nw, force, descs, tp, nactive, total, pass, coefs, final_mode, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

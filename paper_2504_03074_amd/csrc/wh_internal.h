@@ -44,7 +44,7 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
 // hold W^{n-1}, W^n; out_prev/out_cur receive W^{n+ks-1}, W^{n+ks}.  gn[s],
 // wn[s] belong to the step producing W^{n+1+s}.  The last pass of an
 // application uses mode != ACCUMULATE.
-constexpr int kMaxBlockSteps = 4;
+constexpr int kMaxBlockSteps = 8;
 struct BlockCoef {
   double gn[kMaxBlockSteps];
   double wn[kMaxBlockSteps];

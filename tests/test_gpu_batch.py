@@ -122,7 +122,7 @@ def test_batch_autotune_then_apply(torch):
     probs = _mix(4, seed0=620)
     batch = Batch([p.solver("fp64", 4) for p in probs])
     best = batch.autotune(1)
-    assert best["kblock"] in (2, 3, 4) and best["tile"] in (32, 64) and best["ms_per_apply"] > 0
+    assert best["kblock"] in (2, 3, 4, 5, 6) and best["tile"] in (32, 64) and best["ms_per_apply"] > 0
     assert batch.tuning() == dict(kblock=best["kblock"], tile=best["tile"])
     outs = batch.apply([_to_dev(torch, p.v) for p in probs], with_forcing=True)
     for p, o in zip(probs, outs):

@@ -120,9 +120,13 @@ BLOCK_CASES = [
 ]
 
 
-@pytest.mark.parametrize("kblock", [1, 2, 3, 4])
+# steps per launch built for each order: 2..6 for p = 4, 2, 3, 4, 6, 8 for p = 2
+BLOCK_PARAMS = [(k,) + case for case in BLOCK_CASES for k in (1, 2, 3, 4, 5, 6, 8)
+                if k <= 4 or (case[1] == 4 and k in (5, 6)) or (case[1] == 2 and k in (6, 8))]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n,order,c2kind,periods,omega", BLOCK_CASES)
+@pytest.mark.parametrize("kblock,n,order,c2kind,periods,omega", BLOCK_PARAMS)
 def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods, omega):
     """2-D applications with kblock leapfrog steps fused per pass (ragged tiles,
     wall reflections, a grid smaller than the halo) against the oracle."""
@@ -150,8 +154,9 @@ def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods
     assert _walls_zero(fin.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 128), ("fp32", 96), ("fp32", 192)])
-@pytest.mark.parametrize("kblock", [2, 4])
+@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 80), ("fp64", 128), ("fp32", 96),
+                                       ("fp32", 192)])
+@pytest.mark.parametrize("kblock", [2, 4, 6])
 def test_blocked_tile_heights(torch, prec, rows, kblock):
     """Every work-group height of the blocked kernel against the oracle."""
     _say(f"[tile rows] {prec} rows={rows} k={kblock}")
