@@ -502,6 +502,10 @@ def main():
             "launch_us": round(launch_us, 3),
             "launches": prof["launches"],
             "kernel_GPts_per_s": round(prof["point_steps"] / prof["ms"] * 1e-6, 2),
+            # temporal blocking: the same rate against the one-step-per-pass
+            # roofline (56 B per point-step at 8 TB/s = 142.9 GPts/s)
+            "kernel_GPts_vs_unblocked_roofline": round(prof["point_steps"] / prof["ms"] * 1e-6
+                                                       / (HBM_PEAK_GBS / 56.0), 3),
         },
     }
     if args.cpu_baseline:

@@ -265,12 +265,13 @@ WH_API wh_status wh_helmholtz_residual(wh_ctx *ctx, const double *u, double *res
 WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *out);
 
 /* Time-stepping kernel families.
- *   WH_KERNEL_AUTO       library choice (2-D: blocked, 4 steps per pass in
- *                        FP64 and 3 in FP32; 3-D: one node per thread)
+ *   WH_KERNEL_AUTO       library choice (2-D: blocked, 6 steps per pass for
+ *                        p = 4, 8 for p = 2; 3-D: one node per thread)
  *   WH_KERNEL_NODE       one node per thread, one step per launch (2-D, 3-D)
- *   WH_KERNEL_BLOCKED_2D kblock = 2..4 steps per launch; tile = rows of the
- *                        region a work-group loads (FP64: 32, 64, 128;
- *                        FP32: 96, 192; 0 = default), halo kblock*p/2 included
+ *   WH_KERNEL_BLOCKED_2D kblock leapfrog steps per launch (p = 4: 2..6; p = 2:
+ *                        2, 3, 4, 6, 8); tile = rows of the region a
+ *                        work-group loads (FP64: 32, 64, 80; FP32: 96, 192;
+ *                        0 = default), halo kblock*p/2 included
  *   WH_KERNEL_ZCOL_3D    one step per launch; tile = consecutive z nodes per
  *                        thread (4, 8, 16), z-neighbours kept in registers
  * Every family evaluates the same expression per node and step; results

@@ -281,10 +281,13 @@ wh_status drain_profile(wh_ctx *c) {
 }
 
 // Leapfrog steps per blocked launch when the caller does not choose: the
-// fastest measured on MI355X at the default tile heights (2048^2, p = 4:
-// FP64 K = 5, FP32 K = 6; p = 2: K = 8 — more steps per HBM pass outweigh the
-// larger halo until the arithmetic dominates).
-int default_kblock(int order, bool fp32) { return order == 2 ? 8 : (fp32 ? 6 : 5); }
+// fastest measured on MI355X at the default tile heights (2048^2: K = 6 for
+// p = 4, K = 8 for p = 2 — more steps per HBM pass outweigh the larger halo
+// until the arithmetic dominates).
+int default_kblock(int order, bool fp32) {
+  (void)fp32;
+  return order == 2 ? 8 : 6;
+}
 
 struct Tuning {
   int kernel, kblock, tile;
@@ -856,7 +859,7 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
     for (int zb : {4, 8, 16}) cands.push_back({WH_KERNEL_ZCOL_3D, 1, zb});
   } else {
     for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
-      for (int rows : {32, 64, 80, 128, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
+      for (int rows : {32, 64, 80, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
   }
   const Tuning saved{c->kernel, c->kblock, c->tile};
   const bool saved_prof = c->profiling;

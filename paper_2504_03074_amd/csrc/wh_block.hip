@@ -159,7 +159,18 @@ __device__ __forceinline__ void advance_tile_impl(
     }
   }
 
-  const T kx = static_cast<T>(g.kx), ky = static_cast<T>(g.ky), kc = static_cast<T>(g.kc);
+  // c^2 folded into two per-node coefficients: with X, Y the x and y
+  // stencil sums, W^{n+1} = (2 - c^2 kc) W^n + c^2 kx (X + (ky/kx) Y) - W^{n-1}
+  T CA[RS], CB[RS];
+  {
+    const T kx = static_cast<T>(g.kx), kc = static_cast<T>(g.kc);
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      CA[q] = T(2) - C2[q] * kc;
+      CB[q] = C2[q] * kx;
+    }
+  }
+  const T ry = static_cast<T>(g.ky / g.kx);
 
 #pragma unroll
   for (int s = 0; s < K; ++s) {
@@ -191,15 +202,16 @@ __device__ __forceinline__ void advance_tile_impl(
         };
         const T c = cur[q];
         const T xl1 = from_left(c), xr1 = from_right(c);
-        T lap;
+        T S;
         if (P == 2) {
-          lap = kx * (xl1 + xr1) + ky * (row(q - 1) + row(q + 1)) - kc * c;
+          S = (xl1 + xr1) + ry * (row(q - 1) + row(q + 1));
         } else {
           const T xl2 = from_left(xl1), xr2 = from_right(xr1);
-          lap = kx * (T(16) * (xl1 + xr1) - (xl2 + xr2)) +
-                ky * (T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2))) - kc * c;
+          const T X = T(16) * (xl1 + xr1) - (xl2 + xr2);
+          const T Y = T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2));
+          S = X + ry * Y;
         }
-        T nxt = T(2) * c - prv[q] + C2[q] * lap;
+        T nxt = CA[q] * c - prv[q] + CB[q] * S;
         if (FORCE) nxt += gn * F[q];
         prv[q] = nxt;
         ACC[q] += wn * static_cast<double>(nxt);
@@ -369,14 +381,11 @@ hipError_t dispatch_nw(const StepGeom &g, int nw, int ksteps, const void *ip, co
   switch (nw) {
     case 4: return launch_if_fits<T, P, K, 4>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
     case 8: return launch_if_fits<T, P, K, 8>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
-    // FP32's 24-row arrays do not fit groups of more than 8 waves
+    // FP32's 24-row arrays do not fit groups of more than 8 waves; FP64
+    // groups of 16 waves would spill
     case 10:
       if constexpr (sizeof(T) == 8)
         return launch_if_fits<T, P, K, 10>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
-      return hipErrorInvalidValue;
-    case 16:
-      if constexpr (sizeof(T) == 8)
-        return launch_if_fits<T, P, K, 16>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -415,7 +424,7 @@ bool block_config_supported(bool fp32, int order, int K, int rows) {
   const int rs = fp32 ? RowsPerLane<float>::RS : RowsPerLane<double>::RS;
   if (rows % rs != 0) return false;
   const int nw = rows / rs;
-  if (nw != 4 && nw != 8 && !((nw == 10 || nw == 16) && !fp32)) return false;
+  if (nw != 4 && nw != 8 && !(nw == 10 && !fp32)) return false;
   return rows - 2 * K * (order / 2) > 0 && 64 - 2 * K * (order / 2) > 0;
 }
 

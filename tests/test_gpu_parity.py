@@ -154,8 +154,7 @@ def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods
     assert _walls_zero(fin.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 80), ("fp64", 128), ("fp32", 96),
-                                       ("fp32", 192)])
+@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 80), ("fp32", 96), ("fp32", 192)])
 @pytest.mark.parametrize("kblock", [2, 4, 6])
 def test_blocked_tile_heights(torch, prec, rows, kblock):
     """Every work-group height of the blocked kernel against the oracle."""
