@@ -82,7 +82,7 @@ __device__ __forceinline__ int xcd_tile_order(int b, int nblk) {
 // shared by the single-grid and the batched kernels.
 template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR, bool INNER>
 __device__ __forceinline__ void advance_tile_impl(
-    const StepGeom &g, int ksteps, int tx, int ty, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
+    const StepGeom &g, int ksteps, bool first, int tx, int ty, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
     T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
     const T *__restrict__ fg, const BlockCoef &coef, int mode, const double *__restrict__ v,
     double *__restrict__ out, T (*__restrict__ halo)[NW][2][P / 2][64]) {
@@ -114,8 +114,13 @@ __device__ __forceinline__ void advance_tile_impl(
 #pragma unroll
     for (int q = 0; q < RS; ++q) {
       const uint32_t e = base + (uint32_t)q * (uint32_t)g.sy;
-      B[q] = ld_at(in_prev, e);
-      A[q] = ld_at(in_cur, e);
+      if (first) {  // W^0 = v; the half step of step 0 does not read W^{-1}
+        A[q] = static_cast<T>(ld_at(v, e));
+        B[q] = A[q];
+      } else {
+        B[q] = ld_at(in_prev, e);
+        A[q] = ld_at(in_cur, e);
+      }
       C2[q] = CVAR ? ld_at(c2g, e) : static_cast<T>(g.c2const);
       F[q] = FORCE ? ld_at(fg, e) : T(0);
       const int r = wave * RS + q;
@@ -123,7 +128,7 @@ __device__ __forceinline__ void advance_tile_impl(
       if (r >= H && r < H + OY) {
         if (col_in) {
           own |= 1u << q;
-          ACC[q] = ld_at(acc, e);
+          ACC[q] = first ? coef.w0 * static_cast<double>(A[q]) : ld_at(acc, e);
         }
       }
     }
@@ -139,17 +144,22 @@ __device__ __forceinline__ void advance_tile_impl(
       const int iy = reflect(gy, g.ny, s);
       const int64_t id = (int64_t)ix + (int64_t)iy * g.sy;
       const T sg = static_cast<T>(s);
-      B[q] = sg * in_prev[id];
-      A[q] = sg * in_cur[id];
+      const bool wall = col_wall || iy == 0 || iy == g.ny;
+      if (first) {  // wall values of v are ignored (0)
+        A[q] = wall ? T(0) : sg * static_cast<T>(v[id]);
+        B[q] = A[q];
+      } else {
+        B[q] = sg * in_prev[id];
+        A[q] = sg * in_cur[id];
+      }
       C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
       F[q] = FORCE ? sg * fg[id] : T(0);
       const int r = wave * RS + q;
       const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
-      const bool wall = col_wall || iy == 0 || iy == g.ny;
       ACC[q] = 0.0;
       if (in_tile && !wall) {
         own |= 1u << q;
-        ACC[q] = acc[id];
+        ACC[q] = first ? coef.w0 * static_cast<double>(A[q]) : acc[id];
       } else if (in_tile) {
         // wall node owned by this tile: its outputs are exactly 0
         out_prev[id] = T(0);
@@ -211,7 +221,11 @@ __device__ __forceinline__ void advance_tile_impl(
           const T Y = T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2));
           S = X + ry * Y;
         }
-        T nxt = CA[q] * c - prv[q] + CB[q] * S;
+        // step 0 of the first pass is the half step from rest:
+        // W^1 = W^0 + (dt^2/2) L W^0 + g0 f = (CA W^0 + CB S) / 2 + g0 f
+        T nxt;
+        if (s == 0 && first) nxt = T(0.5) * (CA[q] * c + CB[q] * S);
+        else nxt = CA[q] * c - prv[q] + CB[q] * S;
         if (FORCE) nxt += gn * F[q];
         prv[q] = nxt;
         ACC[q] += wn * static_cast<double>(nxt);
@@ -250,7 +264,7 @@ __device__ __forceinline__ void advance_tile_impl(
 }
 
 template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
-__device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, int tx, int ty,
+__device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, bool first, int tx, int ty,
                                              const T *__restrict__ in_prev, const T *__restrict__ in_cur,
                                              T *__restrict__ out_prev, T *__restrict__ out_cur,
                                              double *__restrict__ acc, const T *__restrict__ c2g,
@@ -265,10 +279,10 @@ __device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, int 
   const bool inner = x0 >= 1 && x0 + 63 <= g.nx - 1 && y0 >= 1 && y0 + NW * RS - 1 <= g.ny - 1 &&
                      g.nodes <= (int64_t(1) << 28);
   if (inner)
-    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur, acc,
+    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, ksteps, first, tx, ty, in_prev, in_cur, out_prev, out_cur, acc,
                                                           c2g, fg, coef, mode, v, out, halo);
   else
-    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur,
+    advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, ksteps, first, tx, ty, in_prev, in_cur, out_prev, out_cur,
                                                            acc, c2g, fg, coef, mode, v, out, halo);
 }
 
@@ -281,7 +295,8 @@ __global__ __launch_bounds__(64 * NW) void block_steps_kernel(
   __shared__ T halo[2][NW][2][P / 2][64];  // y-halo rows, double-buffered over steps
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= tiles_total) return;
-  advance_tile<T, P, K, RS, NW, FORCE, CVAR>(g, ksteps, tile % tiles_x, tile / tiles_x, in_prev, in_cur, out_prev,
+  advance_tile<T, P, K, RS, NW, FORCE, CVAR>(g, ksteps, coef.first != 0, tile % tiles_x, tile / tiles_x, in_prev,
+                                             in_cur, out_prev,
                                              out_cur, acc, c2g, fg, coef, mode, v, out, halo);
 }
 
@@ -314,11 +329,12 @@ __global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchD
   T *oc = static_cast<T *>(even ? d.W[3] : d.W[1]);
   const BlockCoef coef = coefs[d.coef_offset + pass];
   const int tx = local % d.tiles_x, ty = local / d.tiles_x;
+  const bool first = coef.first != 0;
   if (d.c2)
-    advance_tile<T, P, K, RS, NW, FORCE, true>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, static_cast<const T *>(d.c2),
+    advance_tile<T, P, K, RS, NW, FORCE, true>(d.g, ks, first, tx, ty, ip, ic, op, oc, d.acc, static_cast<const T *>(d.c2),
                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
   else
-    advance_tile<T, P, K, RS, NW, FORCE, false>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, nullptr,
+    advance_tile<T, P, K, RS, NW, FORCE, false>(d.g, ks, first, tx, ty, ip, ic, op, oc, d.acc, nullptr,
                                                 static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
 }
 
