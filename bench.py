@@ -75,7 +75,7 @@ def log(msg):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "block_steps_kernel_square2048_p4_fp64_hbm_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_03074_amd", "csrc", "wh_block.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_03074_amd", "csrc", "wh_block_impl.h")
 
 
 def measured_traffic(n, precision, tun):

@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwh.so")
 ARCH = "gfx950"
 
-SOURCES = ["wh_kernels.hip", "wh_block.hip", "wh_api.cpp"]
+SOURCES = ["wh_block_f64_p4.hip", "wh_block_f32_p4.hip", "wh_block_f64_p2.hip", "wh_block_f32_p2.hip",
+           "wh_kernels.hip", "wh_block.hip", "wh_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
@@ -31,7 +32,8 @@ def hipcc():
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 4))
     objs = []
     procs = []
     objdir = os.path.join(PKG, "_build")
@@ -45,7 +47,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         cmd = [hipcc()] + [f for f in FLAGS if f != "-shared"] + ["-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden",
-                   "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
+                   "-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

@@ -326,23 +326,21 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
   const int64_t N = (int64_t)c->tp.nt * c->tp.periods;
   const double dt2 = c->tp.dt * c->tp.dt;
   const wh::StepGeom g = geometry(c, dt2);
+  const wh::StepGeom half = geometry(c, 0.5 * dt2);
   const void *c2 = c->c2_is_const ? nullptr : c->c2;
   const void *f = forcing ? c->f : nullptr;
-  const Tuning tu = resolve_tuning(c);
-  const int K = tu.kernel == WH_KERNEL_BLOCKED_2D ? tu.kblock : 1;
-  if (K == 1) {
-    const wh::StepGeom half = geometry(c, 0.5 * dt2);
-    WH_HIP(c, wh::launch_first_step(fp32, half, v, c->W[0], c->W[1], c->acc, c2, f, forcing ? -0.5 * dt2 : 0.0,
-                                    c->wts[0], c->wts[1], c->stream));
-  }
+  WH_HIP(c, wh::launch_first_step(fp32, half, v, c->W[0], c->W[1], c->acc, c2, f, forcing ? -0.5 * dt2 : 0.0,
+                                  c->wts[0], c->wts[1], c->stream));
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (c->profiling) {
     WH_TRY(take_events(c, &ev0, &ev1));
     WH_HIP(c, hipEventRecord(ev0, c->stream));
   }
+  const Tuning tu = resolve_tuning(c);
+  const int K = tu.kernel == WH_KERNEL_BLOCKED_2D ? tu.kblock : 1;
   const double T = (double)state_bytes(c);
   const double aux = (c2 ? T : 0.0) + (f ? T : 0.0);  // c^2 and f reads per node and launch
-  int64_t launches = 0, timed_steps = 0;
+  int64_t launches = 0;
   double bytes_per_node = 0.0;
   void *cur;
   if (K == 1) {
@@ -362,41 +360,35 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
       // W^n, W^{n-1} read, W^{n+1} written, accumulator read and written
       bytes_per_node += 3.0 * T + aux + 16.0;
     }
-    timed_steps = N - 1;
   } else {
-    // passes of K steps from level 0; the first starts from v and takes the
-    // half step to level 1 as its step 0
     void *ip = c->W[0], *ic = c->W[1], *op = c->W[2], *oc = c->W[3];
+    const int64_t total = N - 1;  // steps after the first
     int64_t done = 0;
-    while (done < N) {
-      const int ks = (int)std::min<int64_t>(K, N - done);
+    while (done < total) {
+      const int ks = (int)std::min<int64_t>(K, total - done);
       wh::BlockCoef coef{};
-      coef.first = done == 0 ? 1 : 0;
-      coef.w0 = c->wts[0];
       for (int s = 0; s < ks; ++s) {
-        const int64_t n = done + s;  // step from level n to n + 1
-        coef.gn[s] = forcing ? (n == 0 ? -0.5 * dt2 : c->frc[(size_t)n]) : 0.0;
+        const int64_t n = 1 + done + s;  // step from level n to n + 1
+        coef.gn[s] = forcing ? c->frc[(size_t)n] : 0.0;
         coef.wn[s] = c->wts[(size_t)n + 1];
       }
-      const int m = (done + ks == N) ? mode : wh::ACCUMULATE;
+      const int m = (done + ks == total) ? mode : wh::ACCUMULATE;
       WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, tu.tile, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
                                           c->stream));
-      // first pass: v read, accumulator written; later passes: two levels
-      // and the accumulator read; always two levels written
-      bytes_per_node += (done == 0 ? 8.0 + 8.0 : 2.0 * T + 16.0) + 2.0 * T + aux;
       std::swap(ip, op);
       std::swap(ic, oc);
       done += ks;
       ++launches;
+      // two levels read and two written, accumulator read and written
+      bytes_per_node += 4.0 * T + aux + 16.0;
     }
     cur = ic;
-    timed_steps = N;
   }
   if (c->profiling) {
     WH_HIP(c, hipEventRecord(ev1, c->stream));
     const double interior = interior_nodes(c);
     const double extra = (mode == wh::FINAL_A) ? 8.0 : 0.0;  // v read on the last launch
-    c->pending.push_back({ev0, ev1, launches, interior * (bytes_per_node + extra), interior * (double)timed_steps});
+    c->pending.push_back({ev0, ev1, launches, interior * (bytes_per_node + extra), interior * (double)(N - 1)});
     if (c->pending.size() >= 256) WH_TRY(drain_profile(c));
   }
   if (w_final) WH_HIP(c, wh::launch_from_state(fp32, cur, w_final, c->nodes, c->stream));
@@ -1757,11 +1749,13 @@ struct wh_batch {
   // tables of the current selection (host mirror)
   std::vector<int> ids;
   std::vector<wh::BatchDesc> desc;
+  std::vector<wh::BatchFirst> first;
   std::vector<wh::BatchVec> vecs;
   std::vector<int> prefix, active_at;
-  int maxpasses = 0, red_blocks = 0;
+  int maxpasses = 0, first_blocks = 0, red_blocks = 0;
   // device tables, carved from the bound workspace
   wh::BatchDesc *d_desc = nullptr;
+  wh::BatchFirst *d_first = nullptr;
   wh::BlockCoef *d_coef = nullptr;
   int *d_prefix = nullptr;
   wh::BatchVec *d_vecs = nullptr, *d_vecs_e = nullptr;
@@ -1797,15 +1791,13 @@ void batch_resolve_tuning(wh_batch *b) {
   if (b->rows == 0) b->rows = wh::block_default_rows(fp32);
 }
 
-// passes of K steps over all N = N_t N_p steps (the first pass takes the
-// half step from the iterate)
 int batch_passes(const wh_ctx *c, int K) {
-  const int64_t steps = (int64_t)c->tp.nt * c->tp.periods;
+  const int64_t steps = (int64_t)c->tp.nt * c->tp.periods - 1;
   return (int)((steps + K - 1) / K);
 }
 
 struct BatchLayout {
-  size_t desc, coef, prefix, vecs, vecs_e, part, sc, total;
+  size_t desc, first, coef, prefix, vecs, vecs_e, part, sc, total;
 };
 
 BatchLayout batch_layout(size_t P, size_t ncoef, int red_blocks) {
@@ -1817,6 +1809,7 @@ BatchLayout batch_layout(size_t P, size_t ncoef, int red_blocks) {
     return o;
   };
   L.desc = take(P * sizeof(wh::BatchDesc));
+  L.first = take(P * sizeof(wh::BatchFirst));
   L.coef = take(ncoef * sizeof(wh::BlockCoef));
   L.prefix = take((P + 1) * sizeof(int));
   L.vecs = take(P * sizeof(wh::BatchVec));
@@ -1841,8 +1834,10 @@ wh_status batch_select(wh_batch *b, std::vector<int> ids, const double *const *i
   const size_t n = ids.size();
   b->ids = ids;
   b->desc.assign(n, wh::BatchDesc{});
+  b->first.assign(n, wh::BatchFirst{});
   b->vecs.assign(n, wh::BatchVec{});
   b->prefix.assign(n + 1, 0);
+  b->first_blocks = 0;
   b->red_blocks = 0;
   for (size_t t = 0; t < n; ++t) {
     const int i = ids[t];
@@ -1859,10 +1854,23 @@ wh_status batch_select(wh_batch *b, std::vector<int> ids, const double *const *i
     d.out = out[i];
     d.tiles_x = (int)((c->n[0] + 1 + ox - 1) / ox);
     d.tiles = d.tiles_x * (int)((c->n[1] + 1 + oy - 1) / oy);
-    d.steps = (int)((int64_t)c->tp.nt * c->tp.periods);
+    d.steps = (int)((int64_t)c->tp.nt * c->tp.periods - 1);
     d.passes = b->passes[(size_t)i];
     d.coef_offset = b->coef_off[(size_t)i];
     b->prefix[t + 1] = b->prefix[t] + d.tiles;
+    wh::BatchFirst &f = b->first[t];
+    f.half = geometry(c, 0.5 * dt2);
+    f.v = in[i];
+    f.W0 = c->W[0];
+    f.W1 = c->W[1];
+    f.acc = c->acc;
+    f.c2 = c2;
+    f.f = forcing ? c->f : nullptr;
+    f.g0 = forcing ? -0.5 * dt2 : 0.0;
+    f.w0 = c->wts[0];
+    f.w1 = c->wts[1];
+    f.block_offset = b->first_blocks;
+    b->first_blocks += wh::batch_node_blocks(c->nodes);
     wh::BatchVec &v = b->vecs[t];
     v.x = x ? x[i] : nullptr;
     v.r = c->V;
@@ -1885,6 +1893,7 @@ wh_status batch_select(wh_batch *b, std::vector<int> ids, const double *const *i
   for (auto &v : ve) v.c2 = nullptr;  // Euclidean products
   WH_BHIP(b, hipStreamSynchronize(s));  // host staging below is reused
   WH_BHIP(b, hipMemcpyAsync(b->d_desc, b->desc.data(), n * sizeof(wh::BatchDesc), hipMemcpyHostToDevice, s));
+  WH_BHIP(b, hipMemcpyAsync(b->d_first, b->first.data(), n * sizeof(wh::BatchFirst), hipMemcpyHostToDevice, s));
   WH_BHIP(b, hipMemcpyAsync(b->d_prefix, b->prefix.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   WH_BHIP(b, hipMemcpyAsync(b->d_vecs, b->vecs.data(), n * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
   WH_BHIP(b, hipMemcpyAsync(b->d_vecs_e, ve.data(), n * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
@@ -1902,6 +1911,7 @@ wh_status batch_enqueue_apply(wh_batch *b, bool forcing, int final_mode, hipStre
   const bool fp32 = b->prec == WH_FP32_STATE;
   const int n = (int)b->ids.size();
   if (n == 0) return WH_OK;
+  WH_BHIP(b, wh::launch_batch_first_step(fp32, b->order, b->d_first, n, b->first_blocks, s));
   for (int j = 0; j < b->maxpasses; ++j) {
     const int na = b->active_at[(size_t)j];
     WH_BHIP(b, wh::launch_batch_block_steps(fp32, b->order, b->K, b->rows, forcing, b->d_desc, b->d_prefix, na,
@@ -1975,15 +1985,12 @@ wh_status batch_set_k(wh_batch *b, int K, int rows) {
     wh_ctx *c = b->probs[i];
     b->passes[i] = batch_passes(c, K);
     b->coef_off[i] = (int)coefs.size();
-    const double dt2 = c->tp.dt * c->tp.dt;
     for (int j = 0; j < b->passes[i]; ++j) {
       wh::BlockCoef cf{};
-      cf.first = j == 0 ? 1 : 0;
-      cf.w0 = c->wts[0];
       for (int q = 0; q < K; ++q) {
-        const int64_t n = (int64_t)j * K + q;  // step from level n to n + 1
+        const int64_t n = 1 + (int64_t)j * K + q;
         if (n + 1 >= (int64_t)c->wts.size()) break;
-        cf.gn[q] = n == 0 ? -0.5 * dt2 : c->frc[(size_t)n];
+        cf.gn[q] = c->frc[(size_t)n];
         cf.wn[q] = c->wts[(size_t)n + 1];
       }
       coefs.push_back(cf);
@@ -2111,6 +2118,7 @@ wh_status wh_batch_finalize(wh_batch *b, void *workspace, size_t bytes) {
   const BatchLayout L = batch_layout(P, ncoef, red);
   char *base = static_cast<char *>(workspace);
   b->d_desc = reinterpret_cast<wh::BatchDesc *>(base + L.desc);
+  b->d_first = reinterpret_cast<wh::BatchFirst *>(base + L.first);
   b->d_coef = reinterpret_cast<wh::BlockCoef *>(base + L.coef);
   b->d_prefix = reinterpret_cast<int *>(base + L.prefix);
   b->d_vecs = reinterpret_cast<wh::BatchVec *>(base + L.vecs);

@@ -45,15 +45,9 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
 // wn[s] belong to the step producing W^{n+1+s}.  The last pass of an
 // application uses mode != ACCUMULATE.
 constexpr int kMaxBlockSteps = 8;
-// Coefficients of one blocked pass: step s advances level n0 + s to n0 + s + 1
-// with forcing coefficient gn[s] and adds wn[s] times the new level to the
-// filter; w0 is the weight of level 0, used by the first pass, which starts
-// from the iterate itself and takes the half step to level 1 as its step 0.
 struct BlockCoef {
   double gn[kMaxBlockSteps];
   double wn[kMaxBlockSteps];
-  double w0;
-  int first;  // nonzero for the first pass of an application
 };
 hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, int ksteps, const void *in_prev,
                                  const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
@@ -83,10 +77,10 @@ struct BatchDesc {
   const void *f;        // null: no forcing
   void *W[4];           // state buffers: pass j reads pair j%2, writes the other
   double *acc;          // FP64 filter accumulator
-  const double *v;      // input of the application (first pass, FINAL_A)
+  const double *v;      // input of the application (read by FINAL_A)
   double *out;          // output of the application
   int tiles_x, tiles;   // tile grid of this problem for the batch's (K, rows)
-  int steps;            // leapfrog steps of one application (N)
+  int steps;            // leapfrog steps after the first (N - 1)
   int passes;           // ceil(steps / K)
   int coef_offset;      // index of this problem's first BlockCoef
 };
@@ -96,6 +90,41 @@ hipError_t launch_batch_block_steps(bool fp32, int order, int K, int rows, bool 
                                     const int *tile_prefix, int nactive, int total_tiles, int pass,
                                     const BlockCoef *coefs, int final_mode, hipStream_t s);
 
+// First step of every problem of a batch in one launch.
+struct BatchFirst {
+  StepGeom half;        // stencil scaled by dt^2 / 2
+  const double *v;
+  void *W0, *W1;
+  double *acc;
+  const void *c2;       // null: constant
+  const void *f;        // null: no forcing
+  double g0, w0, w1;
+  int block_offset;     // first thread block of this problem
+};
+hipError_t launch_batch_first_step(bool fp32, int order, const BatchFirst *firsts, int nprob, int total_blocks,
+                                   hipStream_t s);
+int batch_node_blocks(int64_t nodes);
+
+// Per-(precision, order) launchers of the blocked kernels (one translation
+// unit each; the routing above picks one).
+using BlockDispatch = hipError_t (*)(const StepGeom &, int, int, int, const void *, const void *, void *, void *,
+                                     double *, const void *, const void *, const BlockCoef &, int, const double *,
+                                     double *, hipStream_t);
+using BatchDispatch = hipError_t (*)(int, int, bool, const BatchDesc *, const int *, int, int, int, const BlockCoef *,
+                                     int, hipStream_t);
+#define WH_BLOCK_DISPATCH_DECL(name)                                                                            \
+  hipError_t block_dispatch_##name(const StepGeom &g, int K, int nw, int ksteps, const void *in_prev,           \
+                                   const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2, \
+                                   const void *f, const BlockCoef &coef, int mode, const double *v, double *out, \
+                                   hipStream_t s);                                                              \
+  hipError_t batch_dispatch_##name(int K, int nw, bool force, const BatchDesc *descs, const int *tile_prefix,   \
+                                   int nactive, int total_tiles, int pass, const BlockCoef *coefs,               \
+                                   int final_mode, hipStream_t s);
+WH_BLOCK_DISPATCH_DECL(f64_p2)
+WH_BLOCK_DISPATCH_DECL(f64_p4)
+WH_BLOCK_DISPATCH_DECL(f32_p2)
+WH_BLOCK_DISPATCH_DECL(f32_p4)
+#undef WH_BLOCK_DISPATCH_DECL
 
 // Vectors of one problem for the batched Krylov kernels.
 struct BatchVec {

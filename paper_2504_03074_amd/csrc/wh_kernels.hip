@@ -149,6 +149,25 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
   first_step_node<T, DIM, P>(g, i, j, k, v, W0, W1, acc, c2, f, g0, w0, w1);
 }
 
+// Batched first step of 2-D problems: flat node blocks, problem found from
+// the block offsets (ascending).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void batch_first_step_kernel(const BatchFirst *__restrict__ firsts, int nprob) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (firsts[mid].block_offset <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchFirst &d = firsts[lo];
+  const int64_t e = (int64_t)(b - d.block_offset) * 256 + threadIdx.x;
+  if (e >= d.half.nodes) return;
+  const int i = (int)(e % d.half.sy), j = (int)(e / d.half.sy);
+  first_step_node<T, 2, P>(d.half, i, j, 0, d.v, static_cast<T *>(d.W0), static_cast<T *>(d.W1), d.acc,
+                           static_cast<const T *>(d.c2), static_cast<const T *>(d.f), d.g0, d.w0, d.w1);
+}
+
 template <typename T, int DIM, int P>
 __global__ __launch_bounds__(kBlockX *kBlockY) void step_kernel(
     StepGeom g, const T *__restrict__ cur, T *__restrict__ prev_next, double *__restrict__ acc,
@@ -794,6 +813,21 @@ hipError_t launch_helmholtz_residual(const StepGeom &g, const double *u, const v
   else if (fp32_c2) residual_typed<float, double>(g, u, c2, f, omega2, res, s);
   else if (fp32_f) residual_typed<double, float>(g, u, c2, f, omega2, res, s);
   else residual_typed<double, double>(g, u, c2, f, omega2, res, s);
+  return hipGetLastError();
+}
+
+int batch_node_blocks(int64_t nodes) { return (int)((nodes + 255) / 256); }
+
+hipError_t launch_batch_first_step(bool fp32, int order, const BatchFirst *firsts, int nprob, int total_blocks,
+                                   hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  if (fp32) {
+    if (order == 2) batch_first_step_kernel<float, 2><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+    else batch_first_step_kernel<float, 4><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+  } else {
+    if (order == 2) batch_first_step_kernel<double, 2><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+    else batch_first_step_kernel<double, 4><<<total_blocks, 256, 0, s>>>(firsts, nprob);
+  }
   return hipGetLastError();
 }
 
