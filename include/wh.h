@@ -433,7 +433,8 @@ WH_API wh_status wh_batch_create(wh_batch **out, int32_t device, void *stream);
 WH_API void wh_batch_destroy(wh_batch *batch);
 WH_API const char *wh_batch_last_error(const wh_batch *batch);
 
-/* Append a problem; *index (nullable) receives its position. */
+/* Append a problem; *index (nullable) receives its position.  Problems with
+ * deflation set are rejected (WH_EINVAL): the batched solve does not deflate. */
 WH_API wh_status wh_batch_add(wh_batch *batch, wh_ctx *ctx, int32_t *index);
 
 /* Steps per launch and tile rows of the batched blocked kernel (0 = default;

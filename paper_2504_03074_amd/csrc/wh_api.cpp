@@ -2057,6 +2057,7 @@ wh_status wh_batch_add(wh_batch *b, wh_ctx *c, int32_t *index) {
   if (!c->grid_set || !c->ws || !c->c2_set || !c->f_set || !c->freq_set)
     return bfail(b, WH_ESTATE, "problem must have grid, workspace, c^2, source and frequency set");
   if (c->dim != 2) return bfail(b, WH_EINVAL, "batches hold 2-D problems");
+  if (c->defl_count > 0) return bfail(b, WH_EINVAL, "problems with deflation set cannot be batched");
   if (c->ws_restart < 2) return bfail(b, WH_ENOMEM, "problem workspace must be sized for restart >= 2");
   if (c->device != b->device) return bfail(b, WH_EINVAL, "problem on another device");
   for (wh_ctx *o : b->probs)

@@ -139,6 +139,16 @@ def test_deflation_errors_and_clearing(torch):
     tp = oc.time_params(grid, 1.0, 8.0)
     assert info_p["mu_pred"] == pytest.approx(cf.predicted_rate(grid, 1.0, tp)[0], rel=1e-10)
     assert info_d["mu_pred"] < info_p["mu_pred"]
+    from paper_2504_03074_amd import wh as whm
+    s2 = _solver(grid, 1.0, f, 8.0)
+    s2.set_deflation(count=2)
+    b = whm.wh_batch_create(0, None)
+    try:
+        with pytest.raises(WhError) as e:
+            whm.wh_batch_add(b, s2.ctx)  # the batched solve does not deflate
+        assert e.value.status == wh.WH_EINVAL
+    finally:
+        whm.wh_batch_destroy(b)
     g = wl.random_field(grid.shape, seed=552, zero_walls=False)
     s.set_c2(0.8 + 0.1 * g ** 2)
     s.set_frequency(8.0)
