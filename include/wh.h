@@ -270,8 +270,9 @@ WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *o
  *   WH_KERNEL_NODE       one node per thread, one step per launch (2-D, 3-D)
  *   WH_KERNEL_BLOCKED_2D kblock leapfrog steps per launch (p = 4: 2..6; p = 2:
  *                        2, 3, 4, 6, 8); tile = rows of the region a
- *                        work-group loads (FP64: 32, 64, 80; FP32: 96, 192;
- *                        0 = default), halo kblock*p/2 included
+ *                        work-group loads (FP64 p = 4: 40, 80, 100; FP64
+ *                        p = 2: 32, 64, 80; FP32: 96, 192; 0 = default),
+ *                        halo kblock*p/2 included
  *   WH_KERNEL_ZCOL_3D    one step per launch; tile = consecutive z nodes per
  *                        thread (4, 8, 16), z-neighbours kept in registers
  * Every family evaluates the same expression per node and step; results
@@ -438,8 +439,8 @@ WH_API const char *wh_batch_last_error(const wh_batch *batch);
 WH_API wh_status wh_batch_add(wh_batch *batch, wh_ctx *ctx, int32_t *index);
 
 /* Steps per launch and tile rows of the batched blocked kernel (0 = default;
- * same values as WH_KERNEL_BLOCKED_2D up to FP64 64 / FP32 192 rows).  Before
- * wh_batch_finalize. */
+ * same values as WH_KERNEL_BLOCKED_2D up to FP64 80 (p = 4) or 64 (p = 2) and
+ * FP32 192 rows).  Before wh_batch_finalize. */
 WH_API wh_status wh_batch_set_tuning(wh_batch *batch, int32_t kblock, int32_t tile);
 
 /* Bytes of device workspace for the batch's tables (after adding problems). */

@@ -46,7 +46,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         objs.append(obj)
         cmd = [hipcc()] + [f for f in FLAGS if f != "-shared"] + ["-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden",
+            cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden", f"--offload-arch={ARCH}",
                    "-I", INCLUDE, "-I", CSRC, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

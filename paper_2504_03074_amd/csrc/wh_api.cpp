@@ -297,11 +297,12 @@ struct Tuning {
 Tuning resolve_tuning(const wh_ctx *c) {
   const bool fp32 = c->prec == WH_FP32_STATE;
   if (c->kernel == WH_KERNEL_AUTO) {
-    if (c->dim == 2) return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32)};
+    if (c->dim == 2)
+      return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32, c->order)};
     return {WH_KERNEL_NODE, 1, 0};
   }
   if (c->kernel == WH_KERNEL_BLOCKED_2D)
-    return {c->kernel, c->kblock, c->tile > 0 ? c->tile : wh::block_default_rows(fp32)};
+    return {c->kernel, c->kblock, c->tile > 0 ? c->tile : wh::block_default_rows(fp32, c->order)};
   if (c->kernel == WH_KERNEL_ZCOL_3D) return {c->kernel, 1, c->tile > 0 ? c->tile : 8};
   return {WH_KERNEL_NODE, 1, 0};
 }
@@ -859,7 +860,8 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
     for (int zb : {4, 8, 16}) cands.push_back({WH_KERNEL_ZCOL_3D, 1, zb});
   } else {
     for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
-      for (int rows : {32, 64, 80, 96, 192}) cands.push_back({WH_KERNEL_BLOCKED_2D, k, rows});
+      for (int nw : {4, 8, 10})
+        cands.push_back({WH_KERNEL_BLOCKED_2D, k, nw * wh::block_rows_per_lane(c->prec == WH_FP32_STATE, c->order)});
   }
   const Tuning saved{c->kernel, c->kblock, c->tile};
   const bool saved_prof = c->profiling;
@@ -1788,7 +1790,7 @@ wh_status bfail(wh_batch *b, wh_status st, const char *fmt, ...) {
 void batch_resolve_tuning(wh_batch *b) {
   const bool fp32 = b->prec == WH_FP32_STATE;
   if (b->K == 0) b->K = default_kblock(b->order, fp32);
-  if (b->rows == 0) b->rows = wh::block_default_rows(fp32);
+  if (b->rows == 0) b->rows = wh::block_default_rows(fp32, b->order);
 }
 
 int batch_passes(const wh_ctx *c, int K) {
@@ -2077,8 +2079,8 @@ wh_status wh_batch_set_tuning(wh_batch *b, int32_t kblock, int32_t tile) {
   if (b->probs.empty()) return bfail(b, WH_ESTATE, "add problems first");
   const bool fp32 = b->prec == WH_FP32_STATE;
   const int K = kblock == 0 ? default_kblock(b->order, fp32) : kblock;
-  const int rows = tile == 0 ? wh::block_default_rows(fp32) : tile;
-  if (K < 2 || !wh::block_config_supported(fp32, b->order, K, rows) || rows > 8 * (fp32 ? 24 : 8))
+  const int rows = tile == 0 ? wh::block_default_rows(fp32, b->order) : tile;
+  if (K < 2 || !wh::block_config_supported(fp32, b->order, K, rows) || rows > 8 * wh::block_rows_per_lane(fp32, b->order))
     return bfail(b, WH_EINVAL, "kblock %d / tile %d not supported for batches", kblock, tile);
   b->K = K;
   b->rows = rows;
@@ -2316,7 +2318,7 @@ wh_status wh_batch_autotune(wh_batch *b, int32_t applies, int32_t *kblock, int32
   }
   std::vector<int> all(P);
   for (size_t i = 0; i < P; ++i) all[i] = (int)i;
-  const int rows_fp64[] = {32, 64}, rows_fp32[] = {96, 192};
+  const int rpl = wh::block_rows_per_lane(fp32, b->order);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   WH_BHIP(b, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -2328,7 +2330,7 @@ wh_status wh_batch_autotune(wh_batch *b, int32_t applies, int32_t *kblock, int32
   wh_status st = WH_OK;
   for (int K = 2; K <= wh::kMaxBlockSteps && st == WH_OK; ++K) {
     for (int r = 0; r < 2 && st == WH_OK; ++r) {
-      const int rows = fp32 ? rows_fp32[r] : rows_fp64[r];
+      const int rows = (r == 0 ? 4 : 8) * rpl;
       if (!wh::block_config_supported(fp32, b->order, K, rows)) continue;
       st = batch_set_k(b, K, rows);
       if (st == WH_OK) st = batch_select(b, all, in.data(), out.data(), false, nullptr, nullptr, b->own);

@@ -164,15 +164,15 @@ __device__ __forceinline__ void advance_tile_impl(
 
   // c^2 folded into two per-node coefficients: with X, Y the x and y
   // stencil sums, W^{n+1} = (2 - c^2 kc) W^n + c^2 kx (X + (ky/kx) Y) - W^{n-1}
-  T CA[RS], CB[RS];
+  // (2 - c^2 kc) is rebuilt from c^2 kx with one FMA per use, which keeps
+  // one register pair per row free for a taller tile
+  T CB[RS];
   {
-    const T kx = static_cast<T>(g.kx), kc = static_cast<T>(g.kc);
+    const T kx = static_cast<T>(g.kx);
 #pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      CA[q] = T(2) - C2[q] * kc;
-      CB[q] = C2[q] * kx;
-    }
+    for (int q = 0; q < RS; ++q) CB[q] = C2[q] * kx;
   }
+  const T rc = static_cast<T>(g.kc / g.kx);
   const T ry = static_cast<T>(g.ky / g.kx);
 
 #pragma unroll
@@ -214,7 +214,7 @@ __device__ __forceinline__ void advance_tile_impl(
           const T Y = T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2));
           S = X + ry * Y;
         }
-        T nxt = CA[q] * c - prv[q] + CB[q] * S;
+        T nxt = (T(2) - rc * CB[q]) * c - prv[q] + CB[q] * S;
         if (FORCE) nxt += gn * F[q];
         prv[q] = nxt;
         ACC[q] += wn * static_cast<double>(nxt);
@@ -358,20 +358,21 @@ hipError_t launch_typed(const StepGeom &g, int ksteps, const void *in_prev, cons
   return hipGetLastError();
 }
 
-// Rows per lane: FP64 keeps 8 rows per lane and FP32 24 (larger register
-// arrays are not promoted to VGPRs).  Waves per work-group (NW) set the tile
-// height NW * RS; smaller groups let two groups share a CU so that one
-// group's loads overlap the other's arithmetic.
-template <typename T>
+// Rows per lane: FP32 keeps 24 rows per lane, FP64 10 for p = 4 and 8 for
+// p = 2 (the fastest measured; larger register arrays are not promoted to
+// VGPRs, or cost occupancy).  Waves per work-group (NW) set the tile height
+// NW * RS; smaller groups let two groups share a CU so that one group's loads
+// overlap the other's arithmetic.
+template <typename T, int P>
 struct RowsPerLane {
-  static constexpr int RS = sizeof(T) == 8 ? 8 : 24;
+  static constexpr int RS = sizeof(T) == 8 ? (P == 4 ? 10 : 8) : 24;
 };
 
 template <typename T, int P, int K, int NW>
 hipError_t launch_if_fits(const StepGeom &g, int ksteps, const void *ip, const void *ic, void *op, void *oc,
                           double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
                           const double *v, double *out, hipStream_t s) {
-  constexpr int RS = RowsPerLane<T>::RS;
+  constexpr int RS = RowsPerLane<T, P>::RS;
   if constexpr (NW * RS - 2 * K * (P / 2) > 0)
     return launch_typed<T, P, K, RS, NW>(g, ksteps, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
   return hipErrorInvalidValue;
@@ -423,7 +424,7 @@ hipError_t dispatch_k(const StepGeom &g, int K, int nw, int ksteps, const void *
 template <typename T, int P, int K, int NW>
 hipError_t batch_launch_fits(bool force, const BatchDesc *descs, const int *tile_prefix, int nactive, int total,
                              int pass, const BlockCoef *coefs, int final_mode, hipStream_t s) {
-  constexpr int RS = RowsPerLane<T>::RS;
+  constexpr int RS = RowsPerLane<T, P>::RS;
   if constexpr (NW * RS - 2 * K * (P / 2) > 0) {
     const int blocks = ((total + 7) / 8) * 8;
     if (force)

@@ -56,7 +56,9 @@ hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, 
 // rows = tile height of the loaded region (waves per group x rows per lane):
 // FP64 32, 64 or 128; FP32 96 or 192.
 bool block_config_supported(bool fp32, int order, int K, int rows);
-int block_default_rows(bool fp32);
+int block_default_rows(bool fp32, int order);
+// rows of a tile held by one lane (tile rows are multiples of it)
+int block_rows_per_lane(bool fp32, int order);
 // Owned tile (nodes) of one work-group of the blocked kernel.
 void block_tile_shape(bool fp32, int order, int K, int rows, int *owned_x, int *owned_y);
 

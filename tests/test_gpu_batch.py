@@ -104,12 +104,13 @@ def test_batch_apply(torch, prec, order, forcing):
         assert _err(prec, got, single, p.v) <= (1e-14 if prec == "fp64" else 1e-6), p.grid.n
 
 
-@pytest.mark.parametrize("kblock,tile", [(2, 32), (3, 64), (4, 32)])
-def test_batch_apply_tunings(torch, kblock, tile):
+@pytest.mark.parametrize("order,kblock,tile", [(4, 2, 40), (4, 3, 80), (4, 4, 40), (4, 6, 80), (2, 4, 32),
+                                               (2, 8, 64)])
+def test_batch_apply_tunings(torch, order, kblock, tile):
     from paper_2504_03074_amd import Batch
-    _say(f"[batch apply tuning] K={kblock} rows={tile}")
-    probs = _mix(4, seed0=600)
-    batch = Batch([p.solver("fp64", 4) for p in probs], kblock=kblock, tile=tile)
+    _say(f"[batch apply tuning] p={order} K={kblock} rows={tile}")
+    probs = _mix(order, seed0=600)
+    batch = Batch([p.solver("fp64", order) for p in probs], kblock=kblock, tile=tile)
     outs = batch.apply([_to_dev(torch, p.v) for p in probs], with_forcing=True)
     for p, o in zip(probs, outs):
         want = oc.apply(p.grid, p.c2, p.f, p.v, p.tp, with_forcing=True)
@@ -122,7 +123,7 @@ def test_batch_autotune_then_apply(torch):
     probs = _mix(4, seed0=620)
     batch = Batch([p.solver("fp64", 4) for p in probs])
     best = batch.autotune(1)
-    assert best["kblock"] in (2, 3, 4, 5, 6) and best["tile"] in (32, 64) and best["ms_per_apply"] > 0
+    assert best["kblock"] in (2, 3, 4, 5, 6) and best["tile"] in (40, 80) and best["ms_per_apply"] > 0
     assert batch.tuning() == dict(kblock=best["kblock"], tile=best["tile"])
     outs = batch.apply([_to_dev(torch, p.v) for p in probs], with_forcing=True)
     for p, o in zip(probs, outs):

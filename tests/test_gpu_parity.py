@@ -154,13 +154,17 @@ def test_temporally_blocked_apply(torch, kblock, prec, n, order, c2kind, periods
     assert _walls_zero(fin.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec,rows", [("fp64", 32), ("fp64", 64), ("fp64", 80), ("fp32", 96), ("fp32", 192)])
+TILE_ROWS = [("fp64", 4, 40), ("fp64", 4, 80), ("fp64", 4, 100), ("fp64", 2, 32), ("fp64", 2, 64),
+             ("fp64", 2, 80), ("fp32", 4, 96), ("fp32", 4, 192), ("fp32", 2, 96), ("fp32", 2, 192)]
+
+
+@pytest.mark.parametrize("prec,order,rows", TILE_ROWS)
 @pytest.mark.parametrize("kblock", [2, 4, 6])
-def test_blocked_tile_heights(torch, prec, rows, kblock):
+def test_blocked_tile_heights(torch, prec, order, rows, kblock):
     """Every work-group height of the blocked kernel against the oracle."""
-    _say(f"[tile rows] {prec} rows={rows} k={kblock}")
-    grid, c2, f, v = _problem(2, (173, 211), 4, "var", seed=401)
-    s = _solver(2, (173, 211), 4, prec)
+    _say(f"[tile rows] {prec} p={order} rows={rows} k={kblock}")
+    grid, c2, f, v = _problem(2, (173, 211), order, "var", seed=401)
+    s = _solver(2, (173, 211), order, prec)
     s.set_tuning("blocked_2d", kblock, rows)
     assert s.tuning()["tile"] == rows
     s.set_c2(c2)
