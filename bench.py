@@ -459,7 +459,8 @@ def main():
     launch_us = prof["ms"] / prof["launches"] * 1e3
     bytes_per_launch = prof["bytes"] / prof["launches"]
     achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
-    kname = {"blocked_2d": "block_steps_kernel", "node": "step_kernel"}.get(tun["kernel"], tun["kernel"])
+    kname = {"blocked_2d": "block_steps_kernel", "blocked_3d": "block3d_steps_kernel",
+             "node": "step_kernel"}.get(tun["kernel"], tun["kernel"])
 
     result = {
         "metric": "grid-pt updates/s (GPts/s, % HBM roofline) + time to Helmholtz residual 1e-8",

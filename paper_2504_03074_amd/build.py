@@ -17,6 +17,7 @@ LIB = os.path.join(PKG, "libwh.so")
 ARCH = "gfx950"
 
 SOURCES = ["wh_block_f64_p4.hip", "wh_block_f32_p4.hip", "wh_block_f64_p2.hip", "wh_block_f32_p2.hip",
+           "wh_block3d_f64_p4.hip", "wh_block3d_f32_p4.hip", "wh_block3d_f64_p2.hip", "wh_block3d_f32_p2.hip",
            "wh_kernels.hip", "wh_block.hip", "wh_api.cpp"]
 
 FLAGS = [

@@ -293,17 +293,24 @@ struct Tuning {
   int kernel, kblock, tile;
 };
 
+bool tuning_supported(const wh_ctx *c, int kernel, int kblock, int tile);
+
 // The kernel family, steps per launch and tile parameter actually used.
 Tuning resolve_tuning(const wh_ctx *c) {
   const bool fp32 = c->prec == WH_FP32_STATE;
   if (c->kernel == WH_KERNEL_AUTO) {
     if (c->dim == 2)
       return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32, c->order)};
+    const int k3 = c->order == 2 ? 4 : 2;
+    if (tuning_supported(c, WH_KERNEL_BLOCKED_3D, k3, 0))
+      return {WH_KERNEL_BLOCKED_3D, k3, wh::block3d_default_rows(fp32, c->order, k3)};
     return {WH_KERNEL_NODE, 1, 0};
   }
   if (c->kernel == WH_KERNEL_BLOCKED_2D)
     return {c->kernel, c->kblock, c->tile > 0 ? c->tile : wh::block_default_rows(fp32, c->order)};
   if (c->kernel == WH_KERNEL_ZCOL_3D) return {c->kernel, 1, c->tile > 0 ? c->tile : 8};
+  if (c->kernel == WH_KERNEL_BLOCKED_3D)
+    return {c->kernel, c->kblock, c->tile > 0 ? c->tile : wh::block3d_default_rows(fp32, c->order, c->kblock)};
   return {WH_KERNEL_NODE, 1, 0};
 }
 
@@ -316,6 +323,16 @@ bool tuning_supported(const wh_ctx *c, int kernel, int kblock, int tile) {
       return c->dim == 2 && kblock >= 2 && kblock <= wh::kMaxBlockSteps &&
              (tile == 0 || wh::block_config_supported(fp32, c->order, kblock, tile));
     case WH_KERNEL_ZCOL_3D: return c->dim == 3 && kblock <= 1 && (tile == 0 || wh::zcol_supported(tile));
+    case WH_KERNEL_BLOCKED_3D:
+      if (c->dim != 3 || kblock < 1 || kblock > wh::kMaxBlockSteps3d) return false;
+      if ((double)(c->n[0] + 1) * (double)(c->n[1] + 1) * 8.0 >= 4294967296.0) return false;
+      // the last pass of an application may take fewer steps: every smaller
+      // K must be supported with the same rows
+      for (int k = 1; k <= kblock; ++k)
+        if (!wh::block3d_config_supported(fp32, c->order, k,
+                                          tile == 0 ? wh::block3d_default_rows(fp32, c->order, kblock) : tile))
+          return false;
+      return true;
     default: return false;
   }
 }
@@ -338,13 +355,14 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
     WH_HIP(c, hipEventRecord(ev0, c->stream));
   }
   const Tuning tu = resolve_tuning(c);
-  const int K = tu.kernel == WH_KERNEL_BLOCKED_2D ? tu.kblock : 1;
+  const bool blocked = tu.kernel == WH_KERNEL_BLOCKED_2D || tu.kernel == WH_KERNEL_BLOCKED_3D;
+  const int K = blocked ? tu.kblock : 1;
   const double T = (double)state_bytes(c);
   const double aux = (c2 ? T : 0.0) + (f ? T : 0.0);  // c^2 and f reads per node and launch
   int64_t launches = 0;
   double bytes_per_node = 0.0;
   void *cur;
-  if (K == 1) {
+  if (!blocked) {
     void *prev = c->W[0];
     cur = c->W[1];
     for (int64_t n = 1; n < N; ++n) {
@@ -374,8 +392,12 @@ wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double 
         coef.wn[s] = c->wts[(size_t)n + 1];
       }
       const int m = (done + ks == total) ? mode : wh::ACCUMULATE;
-      WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, tu.tile, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
-                                          c->stream));
+      if (tu.kernel == WH_KERNEL_BLOCKED_3D)
+        WH_HIP(c, wh::launch_block_steps_3d(fp32, g, ks, tu.tile, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
+                                            c->stream));
+      else
+        WH_HIP(c, wh::launch_block_steps_2d(fp32, g, K, tu.tile, ks, ip, ic, op, oc, c->acc, c2, f, coef, m, v, out,
+                                            c->stream));
       std::swap(ip, op);
       std::swap(ic, oc);
       done += ks;
@@ -840,6 +862,9 @@ wh_status wh_get_tuning(const wh_ctx *c, int32_t *kernel, int32_t *kblock, int32
     wh::block_tile_shape(c->prec == WH_FP32_STATE, c->order, tu.kblock, tu.tile, &ox, &oy);
   } else if (tu.kernel == WH_KERNEL_ZCOL_3D) {
     oy = 4;
+  } else if (tu.kernel == WH_KERNEL_BLOCKED_3D) {
+    ox = 64 - 2 * tu.kblock * r;
+    oy = tu.tile - 2 * tu.kblock * r;
   }
   (void)r;
   if (kernel) *kernel = tu.kernel;
@@ -858,6 +883,10 @@ wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblo
   std::vector<Tuning> cands{{WH_KERNEL_NODE, 1, 0}};
   if (c->dim == 3) {
     for (int zb : {4, 8, 16}) cands.push_back({WH_KERNEL_ZCOL_3D, 1, zb});
+    const int rs = wh::block3d_rows_per_lane(c->prec == WH_FP32_STATE);
+    for (int k = 2; k <= wh::kMaxBlockSteps3d; ++k)
+      for (int rows : {16, 32})
+        if (rows % rs == 0) cands.push_back({WH_KERNEL_BLOCKED_3D, k, rows});
   } else {
     for (int k = 2; k <= wh::kMaxBlockSteps; ++k)
       for (int nw : {4, 8, 10})

@@ -2,6 +2,7 @@
 // per-(precision, order) translation units (wh_block_<prec>_p<order>.hip).
 #include <hip/hip_runtime.h>
 
+#include "wh_block3d_impl.h"
 #include "wh_block_impl.h"
 
 namespace wh {
@@ -48,6 +49,44 @@ hipError_t launch_batch_block_steps(bool fp32, int order, int K, int rows, bool 
   const BatchDispatch fn = fp32 ? (order == 2 ? batch_dispatch_f32_p2 : batch_dispatch_f32_p4)
                                  : (order == 2 ? batch_dispatch_f64_p2 : batch_dispatch_f64_p4);
   return fn(K, nw, force, descs, tile_prefix, nactive, total_tiles, pass, coefs, final_mode, s);
+}
+
+// ---- 3-D: z-pipelined blocked kernel ----
+int block3d_rows_per_lane(bool fp32) { return fp32 ? Rows3d<float>::RS : Rows3d<double>::RS; }
+
+// LDS of the double-buffered y-halo of all K levels; kept within 64 KB
+static int block3d_lds(bool fp32, int order, int K, int nw) {
+  return 2 * K * nw * 2 * (order / 2) * 64 * (fp32 ? 4 : 8);
+}
+
+bool block3d_config_supported(bool fp32, int order, int K, int rows) {
+  if (!(order == 2 || order == 4) || K < 1 || K > kMaxBlockSteps3d) return false;
+  const int rs = block3d_rows_per_lane(fp32);
+  if (rows % rs != 0) return false;
+  const int nw = rows / rs;
+  if (fp32 ? (nw != 8 && nw != 16) : (nw != 4 && nw != 8)) return false;
+  const int H = K * (order / 2);
+  return rows - 2 * H > 0 && 64 - 2 * H > 0 && block3d_lds(fp32, order, K, nw) <= 65536;
+}
+
+// the larger group where it fits (FP32 16 waves, FP64 8)
+int block3d_default_rows(bool fp32, int order, int K) {
+  const int rs = block3d_rows_per_lane(fp32);
+  const int big = (fp32 ? 16 : 8) * rs;
+  return block3d_config_supported(fp32, order, K, big) ? big : big / 2;
+}
+
+hipError_t launch_block_steps_3d(bool fp32, const StepGeom &g, int K, int rows, const void *in_prev,
+                                 const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
+                                 const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
+                                 hipStream_t s) {
+  if (g.dim != 3 || !block3d_config_supported(fp32, g.order, K, rows)) return hipErrorInvalidValue;
+  // node offsets within a plane are 32-bit byte offsets
+  if ((double)g.sz * (fp32 ? 4.0 : 8.0) >= 4294967296.0) return hipErrorInvalidValue;
+  const int nw = rows / block3d_rows_per_lane(fp32);
+  const Block3dDispatch fn = fp32 ? (g.order == 2 ? block3d_dispatch_f32_p2 : block3d_dispatch_f32_p4)
+                                   : (g.order == 2 ? block3d_dispatch_f64_p2 : block3d_dispatch_f64_p4);
+  return fn(g, K, nw, in_prev, in_cur, out_prev, out_cur, acc, c2, f, coef, mode, v, out, s);
 }
 
 }  // namespace wh

@@ -1,0 +1,429 @@
+// Temporally blocked leapfrog + filter kernel for 3-D grids (gfx950):
+// templates shared by the per-(precision, order) translation units.
+//
+// A work-group owns an (x, y) tile over a segment of z planes and streams
+// through the segment one plane at a time.  K leapfrog steps of the explicit
+// scheme (Sec. 4.2.1, eq. WaveSchemeexplicit) are pipelined along z: in every
+// iteration one new plane of W^{n-1}, W^n and c^2 is loaded, and step k
+// (k = 1..K) produces level n+k on the plane k*r behind the newest one, from
+// level n+k-1 on the planes (k-1)*r .. (k+1)*r behind it (r = p/2), which
+// are all on chip by then.  Each time level keeps the planes it still feeds
+// (its z-stencil, the step two levels up, and the filter sum) in a ring of
+// registers, so every node of W^{n-1}, W^n, c^2 and the accumulator is read
+// once and W^{n+K-1}, W^{n+K} and the accumulator are written once per K
+// steps.  What is loaded twice is the x-y halo H = K*r (by the neighbouring
+// tiles) and the 2H planes each segment needs beyond its own.
+//
+// Lanes hold x columns (DPP moves give the x neighbours); each wave holds RS
+// consecutive y rows of its columns (the lane's own rows give the y
+// neighbours, and the r edge rows of every level cross waves through a
+// double-buffered LDS array: one barrier per plane).  Values near the tile
+// edges go wrong by r nodes per step, so after K steps the owned
+// (64 - 2H) x (NW*RS - 2H) tile is exact.  Walls: nodes beyond a wall are
+// loaded as odd reflections (c^2 even) in all three axes and the update is
+// the same expression on symmetric neighbour-pair sums everywhere, so
+// mirrored nodes stay exact negatives and wall nodes exact zeros; owned wall
+// nodes are written as 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wh_block_impl.h"
+#include "wh_internal.h"
+
+namespace wh {
+namespace {
+
+// Planes of each time level held by the z pipeline of K steps of order P
+// (newest plane in slot 0).
+template <int P, int K>
+struct Pipe3d {
+  static constexpr int R = P / 2;
+  static constexpr int H = K * R;
+  // W^{n-1}: read by step 1 on the plane r behind the newest
+  static constexpr int LPREV = R + 1;
+  // level n + j (j = 0..K-1): step j+1 reads slots 0..2r (its z-stencil),
+  // step j+2 slot 2r (the previous level), the filter sum slot (K - j) r
+  static constexpr int len(int j) {
+    return j == 0 ? 2 * R + 1 : (((K - j) * R > 2 * R ? (K - j) * R : 2 * R) + 1);
+  }
+  static constexpr int off(int j) {
+    int o = 0;
+    for (int i = 0; i < j; ++i) o += len(i);
+    return o;
+  }
+  static constexpr int LV = off(K);
+  // c^2 kx on the planes 0 .. K r behind the newest
+  static constexpr int LC = H + 1;
+};
+
+template <typename T, int P, int K, int NW>
+constexpr int block3d_lds_bytes() {
+  return 2 * K * NW * 2 * (P / 2) * 64 * (int)sizeof(T);
+}
+
+// K leapfrog steps of the owned planes [z0, z1) of tile (tx, ty).
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR, bool INNER>
+__device__ __forceinline__ void advance_column_impl(
+    const StepGeom &g, int tx, int ty, int z0, int z1, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
+    T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
+    const T *__restrict__ fg, const BlockCoef &coef, int mode, const double *__restrict__ v,
+    double *__restrict__ out, T (*__restrict__ halo)[K][NW][2][P / 2][64]) {
+  using PP = Pipe3d<P, K>;
+  constexpr int R = PP::R;
+  constexpr int H = PP::H;
+  constexpr int OX = 64 - 2 * H;
+  constexpr int OY = NW * RS - 2 * H;
+  static_assert(OX > 0 && OY > 0, "tile too small for the halo");
+  static_assert(RS >= R, "each wave must hold at least r rows");
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gx = tx * OX - H + lane;
+  const int gy0 = ty * OY - H + wave * RS;
+
+  // node offset of (x, y) within a plane, reflection sign, ownership, walls
+  uint32_t off[RS];
+  T sgn[RS];
+  uint32_t own = 0, wall = 0;
+  {
+    float sx = 1.0f;
+    const int ix = INNER ? gx : reflect(gx, g.nx, sx);
+    const bool col_owned = lane >= H && lane < H + OX && gx <= g.nx;
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      float s = sx;
+      const int gy = gy0 + q;
+      const int iy = INNER ? gy : reflect(gy, g.ny, s);
+      off[q] = (uint32_t)ix + (uint32_t)iy * (uint32_t)g.sy;
+      sgn[q] = static_cast<T>(s);
+      const int row = wave * RS + q;
+      if (col_owned && row >= H && row < H + OY && gy <= g.ny) own |= 1u << q;
+      if (ix == 0 || ix == g.nx || iy == 0 || iy == g.ny) wall |= 1u << q;
+    }
+  }
+
+  T WP[RS][PP::LPREV];
+  T WV[RS][PP::LV];
+  T CB[RS][CVAR ? PP::LC : 1];
+#pragma unroll
+  for (int q = 0; q < RS; ++q) {
+#pragma unroll
+    for (int d = 0; d < PP::LPREV; ++d) WP[q][d] = T(0);
+#pragma unroll
+    for (int d = 0; d < PP::LV; ++d) WV[q][d] = T(0);
+#pragma unroll
+    for (int d = 0; d < (CVAR ? PP::LC : 1); ++d) CB[q][d] = T(0);
+  }
+
+  // c^2 folded as in the 2-D kernel: with X, Y, Z the stencil sums along
+  // x, y, z, W^{n+1} = (2 - c^2 kc) W^n + c^2 kx (X + (ky/kx) Y + (kz/kx) Z) - W^{n-1}
+  const T kx = static_cast<T>(g.kx);
+  const T rc = static_cast<T>(g.kc / g.kx);
+  const T ry = static_cast<T>(g.ky / g.kx);
+  const T rz = static_cast<T>(g.kz / g.kx);
+  const T cb_const = static_cast<T>(g.c2const * g.kx);
+  const int64_t sz = g.sz;
+  const int nit = (z1 - z0) + 2 * H;
+
+  // Loads run one plane ahead: the next plane of W^{n-1}, W^n and c^2, and
+  // the accumulator of the output plane, are in flight during the LDS
+  // exchange and the K steps of the current plane.
+  T NA[RS], NB[RS], NC[CVAR ? RS : 1];
+  auto load_plane = [&](int zl) -> T {
+    float szs = 1.0f;
+    const int iz = reflect(zl, g.nz, szs);  // odd reflection across the z walls
+    const int64_t pb = (int64_t)iz * sz;
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      NA[q] = ld_at(in_cur + pb, off[q]);
+      NB[q] = ld_at(in_prev + pb, off[q]);
+      if constexpr (CVAR) NC[q] = ld_at(c2g + pb, off[q]);
+    }
+    return static_cast<T>(szs);
+  };
+  T nsg = load_plane(z0 - H);
+
+  for (int it = 0; it < nit; ++it) {
+    const int zp = z0 - H + it;  // plane entering the pipeline in this iteration
+    // age every ring by one plane
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+#pragma unroll
+      for (int d = PP::LPREV - 1; d > 0; --d) WP[q][d] = WP[q][d - 1];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int d = PP::len(j) - 1; d > 0; --d) WV[q][PP::off(j) + d] = WV[q][PP::off(j) + d - 1];
+      }
+      if constexpr (CVAR) {
+#pragma unroll
+        for (int d = PP::LC - 1; d > 0; --d) CB[q][d] = CB[q][d - 1];
+      }
+    }
+    // take the staged plane zp (reflection signs: uniform in z, per row in x, y)
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      WV[q][0] = NA[q];
+      WP[q][0] = NB[q];
+      if constexpr (CVAR) CB[q][0] = NC[q] * kx;
+    }
+    if (!INNER) {
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        WV[q][0] *= sgn[q];
+        WP[q][0] *= sgn[q];
+      }
+    }
+    if (nsg < T(0)) {
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        WV[q][0] = -WV[q][0];
+        WP[q][0] = -WP[q][0];
+      }
+    }
+    if (it + 1 < nit) nsg = load_plane(zp + 1);
+    // accumulator of the plane this iteration completes
+    const int zo = zp - H;
+    const bool out_plane = zo >= z0 && zo < z1;
+    const bool zwall = zo == 0 || zo == g.nz;
+    const int64_t ob = (int64_t)zo * sz;
+    double AC[RS];
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      AC[q] = 0.0;
+      if (out_plane && !zwall && ((own & ~wall) >> q) & 1u) AC[q] = ld_at(acc + ob, off[q]);
+    }
+    // y-halo: every level's centre plane (slot r) is what its step needs
+    const int hb = it & 1;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        halo[hb][j][wave][0][m][lane] = WV[m][PP::off(j) + R];
+        halo[hb][j][wave][1][m][lane] = WV[RS - R + m][PP::off(j) + R];
+      }
+    }
+    __syncthreads();
+
+    T last[RS];  // level n + K on the output plane
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+      const int j = k - 1;  // input level n + k - 1
+      T up[R], dn[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        up[m] = wave > 0 ? halo[hb][j][wave - 1][1][m][lane] : T(0);
+        dn[m] = wave < NW - 1 ? halo[hb][j][wave + 1][0][m][lane] : T(0);
+      }
+      const T gn = static_cast<T>(coef.gn[k - 1]);
+      // forcing on the plane of this step (FORCE only: right-hand sides)
+      const T *fp = nullptr;
+      T fs = T(1);
+      if constexpr (FORCE) {
+        float s = 1.0f;
+        const int izk = reflect(zp - k * R, g.nz, s);
+        fp = fg + (int64_t)izk * sz;
+        fs = static_cast<T>(s);
+      }
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        auto row = [&](int qq) -> T {
+          if (qq < 0) return up[qq + R];
+          if (qq >= RS) return dn[qq - RS];
+          return WV[qq][PP::off(j) + R];
+        };
+        const T c = WV[q][PP::off(j) + R];
+        const T xl1 = from_left(c), xr1 = from_right(c);
+        T S;
+        if constexpr (P == 2) {
+          S = (xl1 + xr1) + ry * (row(q - 1) + row(q + 1)) +
+              rz * (WV[q][PP::off(j) + R - 1] + WV[q][PP::off(j) + R + 1]);
+        } else {
+          const T xl2 = from_left(xl1), xr2 = from_right(xr1);
+          const T X = T(16) * (xl1 + xr1) - (xl2 + xr2);
+          const T Y = T(16) * (row(q - 1) + row(q + 1)) - (row(q - 2) + row(q + 2));
+          const T Z = T(16) * (WV[q][PP::off(j) + R - 1] + WV[q][PP::off(j) + R + 1]) -
+                      (WV[q][PP::off(j) + R - 2] + WV[q][PP::off(j) + R + 2]);
+          S = X + ry * Y + rz * Z;
+        }
+        const T prv = k == 1 ? WP[q][R] : WV[q][PP::off(k >= 2 ? k - 2 : 0) + 2 * R];
+        const T cb = CVAR ? CB[q][CVAR ? k * R : 0] : cb_const;
+        T nxt = (T(2) - rc * cb) * c - prv + cb * S;
+        if constexpr (FORCE) {
+          T fv = ld_at(fp, off[q]);
+          if (!INNER) fv *= sgn[q];
+          nxt += gn * (fs * fv);
+        }
+        if (k < K) WV[q][PP::off(k < K ? k : 0)] = nxt;
+        else last[q] = nxt;
+      }
+    }
+
+    // the output plane: level n + K just produced, level n + j on slot (K - j) r
+    if (out_plane) {
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        if (!((own >> q) & 1u)) continue;
+        const uint32_t e = off[q];
+        if (zwall || ((wall >> q) & 1u)) {
+          st_at(out_prev + ob, e, T(0));
+          st_at(out_cur + ob, e, T(0));
+          if (mode != ACCUMULATE) st_at(out + ob, e, 0.0);
+          continue;
+        }
+        double a = AC[q];
+#pragma unroll
+        for (int k = 1; k < K; ++k) a += coef.wn[k - 1] * static_cast<double>(WV[q][PP::off(k) + (K - k) * R]);
+        a += coef.wn[K - 1] * static_cast<double>(last[q]);
+        st_at(out_cur + ob, e, last[q]);
+        st_at(out_prev + ob, e, WV[q][PP::off(K - 1) + R]);
+        if (mode == ACCUMULATE) st_at(acc + ob, e, a);
+        else if (mode == FINAL_FILTER) st_at(out + ob, e, a);
+        else st_at(out + ob, e, ld_at(v + ob, e) - a);
+      }
+    }
+  }
+}
+
+template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
+__global__ __launch_bounds__(64 * NW) void block3d_steps_kernel(
+    StepGeom g, int tiles_x, int tiles_xy, int zlen, int tiles_total, const T *__restrict__ in_prev,
+    const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
+    const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
+    double *__restrict__ out) {
+  __shared__ T halo[2][K][NW][2][P / 2][64];
+  const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
+  if (tile >= tiles_total) return;
+  const int seg = tile / tiles_xy;
+  const int txy = tile - seg * tiles_xy;
+  const int tx = txy % tiles_x, ty = txy / tiles_x;
+  const int z0 = seg * zlen;
+  const int z1 = min(z0 + zlen, g.nz + 1);
+  constexpr int H = K * (P / 2);
+  constexpr int OX = 64 - 2 * H;
+  constexpr int OY = NW * RS - 2 * H;
+  const int x0 = tx * OX - H, y0 = ty * OY - H;
+  const bool inner = x0 >= 1 && x0 + 63 <= g.nx - 1 && y0 >= 1 && y0 + NW * RS - 1 <= g.ny - 1;
+  if (inner)
+    advance_column_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
+                                                            acc, c2g, fg, coef, mode, v, out, halo);
+  else
+    advance_column_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
+                                                             acc, c2g, fg, coef, mode, v, out, halo);
+}
+
+// Rows per lane of the 3-D kernel (the rings hold 15-34 planes per row):
+// FP32 2 rows in groups of 8 or 16 waves, FP64 4 rows in groups of 4 or 8
+// waves, the fastest measured (larger register arrays cost occupancy; FP64
+// groups of 16 waves spill).
+#ifndef WH_BLOCK3D_RS_F32
+#define WH_BLOCK3D_RS_F32 2
+#endif
+#ifndef WH_BLOCK3D_RS_F64
+#define WH_BLOCK3D_RS_F64 4
+#endif
+template <typename T>
+struct Rows3d {
+  static constexpr int RS = sizeof(T) == 8 ? WH_BLOCK3D_RS_F64 : WH_BLOCK3D_RS_F32;
+};
+
+// Segment length along z: enough segments that the launch has about
+// `kTargetGroups` work-groups, but segments no shorter than 4H planes
+// (each segment loads 2H planes beyond its own).
+#ifndef WH_BLOCK3D_TARGET_GROUPS
+#define WH_BLOCK3D_TARGET_GROUPS 2048
+#endif
+inline int block3d_zlen(int nz, int tiles_xy, int H) {
+  const int planes = nz + 1;
+  const int min_len = 4 * H > 8 ? 4 * H : 8;
+  int nseg = (WH_BLOCK3D_TARGET_GROUPS + tiles_xy - 1) / tiles_xy;
+  const int max_seg = (planes + min_len - 1) / min_len;
+  if (nseg > max_seg) nseg = max_seg;
+  if (nseg < 1) nseg = 1;
+  return (planes + nseg - 1) / nseg;
+}
+
+template <typename T, int P, int K, int NW>
+hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in_cur, void *out_prev, void *out_cur,
+                          double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
+                          const double *v, double *out, hipStream_t s) {
+  constexpr int RS = Rows3d<T>::RS;
+  if constexpr (NW * RS - 2 * K * (P / 2) > 0 && block3d_lds_bytes<T, P, K, NW>() <= 65536) {
+    constexpr int H = K * (P / 2);
+    constexpr int OX = 64 - 2 * H;
+    constexpr int OY = NW * RS - 2 * H;
+    const int tiles_x = (g.nx + 1 + OX - 1) / OX;
+    const int tiles_y = (g.ny + 1 + OY - 1) / OY;
+    const int tiles_xy = tiles_x * tiles_y;
+    const int zlen = block3d_zlen(g.nz, tiles_xy, H);
+    const int nseg = (g.nz + 1 + zlen - 1) / zlen;
+    const int64_t tiles64 = (int64_t)tiles_xy * nseg;
+    if (tiles64 > (int64_t)1 << 30) return hipErrorInvalidValue;
+    const int tiles = (int)tiles64;
+    const int blocks = ((tiles + 7) / 8) * 8;
+    const T *ip = static_cast<const T *>(in_prev);
+    const T *ic = static_cast<const T *>(in_cur);
+    T *op = static_cast<T *>(out_prev);
+    T *oc = static_cast<T *>(out_cur);
+    const T *cc = static_cast<const T *>(c2);
+    const T *ff = static_cast<const T *>(f);
+    dim3 grid(blocks), block(64 * NW);
+    if (f && c2)
+      block3d_steps_kernel<T, P, K, RS, NW, true, true><<<grid, block, 0, s>>>(g, tiles_x, tiles_xy, zlen, tiles, ip,
+                                                                              ic, op, oc, acc, cc, ff, coef, mode, v,
+                                                                              out);
+    else if (f)
+      block3d_steps_kernel<T, P, K, RS, NW, true, false><<<grid, block, 0, s>>>(g, tiles_x, tiles_xy, zlen, tiles, ip,
+                                                                               ic, op, oc, acc, cc, ff, coef, mode, v,
+                                                                               out);
+    else if (c2)
+      block3d_steps_kernel<T, P, K, RS, NW, false, true><<<grid, block, 0, s>>>(g, tiles_x, tiles_xy, zlen, tiles, ip,
+                                                                               ic, op, oc, acc, cc, ff, coef, mode, v,
+                                                                               out);
+    else
+      block3d_steps_kernel<T, P, K, RS, NW, false, false><<<grid, block, 0, s>>>(g, tiles_x, tiles_xy, zlen, tiles,
+                                                                                ip, ic, op, oc, acc, cc, ff, coef,
+                                                                                mode, v, out);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P, int K>
+hipError_t dispatch3d_nw(const StepGeom &g, int nw, const void *ip, const void *ic, void *op, void *oc, double *acc,
+                         const void *c2, const void *f, const BlockCoef &coef, int mode, const double *v,
+                         double *out, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    switch (nw) {
+      case 4: return launch3d_typed<T, P, K, 4>(g, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      case 8: return launch3d_typed<T, P, K, 8>(g, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (nw) {
+      case 8: return launch3d_typed<T, P, K, 8>(g, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      case 16: return launch3d_typed<T, P, K, 16>(g, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+// K = 1..4 (a pass of fewer steps than the tuned K uses the smaller kernel)
+template <typename T, int P>
+hipError_t dispatch3d_k(const StepGeom &g, int K, int nw, const void *ip, const void *ic, void *op, void *oc,
+                        double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
+                        const double *v, double *out, hipStream_t s) {
+  switch (K) {
+    case 1: return dispatch3d_nw<T, P, 1>(g, nw, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 2: return dispatch3d_nw<T, P, 2>(g, nw, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 3: return dispatch3d_nw<T, P, 3>(g, nw, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    case 4: return dispatch3d_nw<T, P, 4>(g, nw, ip, ic, op, oc, acc, c2, f, coef, mode, v, out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+}  // namespace wh

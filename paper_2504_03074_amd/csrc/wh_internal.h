@@ -54,13 +54,26 @@ hipError_t launch_block_steps_2d(bool fp32, const StepGeom &g, int K, int rows, 
                                  const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
                                  hipStream_t s);
 // rows = tile height of the loaded region (waves per group x rows per lane):
-// FP64 32, 64 or 128; FP32 96 or 192.
+// FP64 p = 4: 40, 80, 100; FP64 p = 2: 32, 64, 80; FP32 96 or 192.
 bool block_config_supported(bool fp32, int order, int K, int rows);
 int block_default_rows(bool fp32, int order);
 // rows of a tile held by one lane (tile rows are multiples of it)
 int block_rows_per_lane(bool fp32, int order);
 // Owned tile (nodes) of one work-group of the blocked kernel.
 void block_tile_shape(bool fp32, int order, int K, int rows, int *owned_x, int *owned_y);
+
+// Temporally blocked steps for 3-D grids: K (1..4) leapfrog steps per pass,
+// pipelined along z over (x, y) tiles of 64 columns x `rows` rows (16 or 32)
+// and segments of z planes.  Same buffers, modes and
+// coefficients as launch_block_steps_2d; every pass takes exactly K steps.
+hipError_t launch_block_steps_3d(bool fp32, const StepGeom &g, int K, int rows, const void *in_prev,
+                                 const void *in_cur, void *out_prev, void *out_cur, double *acc, const void *c2,
+                                 const void *f, const BlockCoef &coef, int mode, const double *v, double *out,
+                                 hipStream_t s);
+bool block3d_config_supported(bool fp32, int order, int K, int rows);
+int block3d_default_rows(bool fp32, int order, int K);
+int block3d_rows_per_lane(bool fp32);
+constexpr int kMaxBlockSteps3d = 4;
 
 // One leapfrog step for a 3-D grid with zb consecutive z nodes per thread
 // (zb in {4, 8, 16}); same arguments and modes as launch_step.
@@ -112,6 +125,9 @@ int batch_node_blocks(int64_t nodes);
 using BlockDispatch = hipError_t (*)(const StepGeom &, int, int, int, const void *, const void *, void *, void *,
                                      double *, const void *, const void *, const BlockCoef &, int, const double *,
                                      double *, hipStream_t);
+using Block3dDispatch = hipError_t (*)(const StepGeom &, int, int, const void *, const void *, void *, void *,
+                                       double *, const void *, const void *, const BlockCoef &, int, const double *,
+                                       double *, hipStream_t);
 using BatchDispatch = hipError_t (*)(int, int, bool, const BatchDesc *, const int *, int, int, int, const BlockCoef *,
                                      int, hipStream_t);
 #define WH_BLOCK_DISPATCH_DECL(name)                                                                            \
@@ -122,6 +138,15 @@ using BatchDispatch = hipError_t (*)(int, int, bool, const BatchDesc *, const in
   hipError_t batch_dispatch_##name(int K, int nw, bool force, const BatchDesc *descs, const int *tile_prefix,   \
                                    int nactive, int total_tiles, int pass, const BlockCoef *coefs,               \
                                    int final_mode, hipStream_t s);
+#define WH_BLOCK3D_DISPATCH_DECL(name)                                                                          \
+  hipError_t block3d_dispatch_##name(const StepGeom &g, int K, int nw, const void *in_prev, const void *in_cur, \
+                                     void *out_prev, void *out_cur, double *acc, const void *c2, const void *f,  \
+                                     const BlockCoef &coef, int mode, const double *v, double *out, hipStream_t s);
+WH_BLOCK3D_DISPATCH_DECL(f64_p2)
+WH_BLOCK3D_DISPATCH_DECL(f64_p4)
+WH_BLOCK3D_DISPATCH_DECL(f32_p2)
+WH_BLOCK3D_DISPATCH_DECL(f32_p4)
+#undef WH_BLOCK3D_DISPATCH_DECL
 WH_BLOCK_DISPATCH_DECL(f64_p2)
 WH_BLOCK_DISPATCH_DECL(f64_p4)
 WH_BLOCK_DISPATCH_DECL(f32_p2)

@@ -19,8 +19,8 @@ WH_OK, WH_EINVAL, WH_ENOMEM, WH_EDEVICE, WH_EUNSTABLE, WH_ENOTCONV, WH_ENONFINIT
 WH_FP64, WH_FP32_STATE = 0, 1
 WH_SOLVER_FPI, WH_SOLVER_GMRES, WH_SOLVER_CG = 0, 1, 2
 WH_MAX_RESTART = 4096
-WH_KERNEL_AUTO, WH_KERNEL_NODE, WH_KERNEL_BLOCKED_2D, WH_KERNEL_ZCOL_3D = 0, 1, 2, 3
-KERNEL_NAMES = {0: "auto", 1: "node", 2: "blocked_2d", 3: "zcol_3d"}
+WH_KERNEL_AUTO, WH_KERNEL_NODE, WH_KERNEL_BLOCKED_2D, WH_KERNEL_ZCOL_3D, WH_KERNEL_BLOCKED_3D = 0, 1, 2, 3, 4
+KERNEL_NAMES = {0: "auto", 1: "node", 2: "blocked_2d", 3: "zcol_3d", 4: "blocked_3d"}
 KERNEL_IDS = {v: k for k, v in KERNEL_NAMES.items()}
 
 
@@ -545,7 +545,7 @@ class Solver:
         return wh_get_time_params(self.ctx).as_dict()
 
     def set_tuning(self, kernel="auto", kblock=0, tile=0):
-        """kernel: "auto", "node", "blocked_2d" or "zcol_3d"."""
+        """kernel: "auto", "node", "blocked_2d", "zcol_3d" or "blocked_3d"."""
         wh_set_tuning(self.ctx, KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel), kblock, tile)
 
     def tuning(self):

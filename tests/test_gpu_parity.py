@@ -200,6 +200,75 @@ def test_3d_kernel_variants(torch, kernel, tile, prec, n, order, periods):
     assert _walls_zero(gotA)
 
 
+# (prec, order, K, rows) of the z-pipelined 3-D kernel: every supported
+# steps-per-pass count with the default tile and both tile heights where they
+# fit the LDS budget
+BLOCKED_3D = [("fp32", 2, k, 32) for k in (1, 2, 3, 4)] + [("fp32", 2, k, 16) for k in (2, 4)] + \
+             [("fp32", 4, k, 32) for k in (1, 2)] + [("fp32", 4, k, 16) for k in (1, 2, 3)] + \
+             [("fp64", 2, k, 32) for k in (1, 2, 3, 4)] + [("fp64", 2, k, 16) for k in (2, 4)] + \
+             [("fp64", 4, k, 32) for k in (1, 2)] + [("fp64", 4, 3, 16)]
+
+
+@pytest.mark.parametrize("prec,order,kblock,rows", BLOCKED_3D)
+def test_3d_blocked_apply(torch, prec, order, kblock, rows):
+    """3-D temporally blocked kernel (K steps pipelined along z): several x
+    and y tiles (inner and wall tiles), several z segments, a step count that
+    leaves a shorter last pass; W_h(v, f) with variable c^2 and A v."""
+    n = (130, 61, 45)
+    _say(f"[3d blocked] {prec} p={order} K={kblock} rows={rows}")
+    grid, c2, f, v = _problem(3, n, order, "var", seed=611 + order)
+    s = _solver(3, n, order, prec)
+    s.set_tuning("blocked_3d", kblock, rows)
+    t = s.tuning()
+    assert t["kernel"] == "blocked_3d" and t["kblock"] == kblock and t["tile"] == rows
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(13.0)
+    tp = oc.time_params(grid, c2, 13.0)
+    vd = _to_dev(torch, v)
+    got = s.apply(vd, with_forcing=True).cpu().numpy()
+    assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
+    assert _walls_zero(got)
+    gotA = s.apply_A(vd).cpu().numpy()
+    assert _err(prec, gotA, oc.apply_A(grid, c2, v, tp), v) <= TOL[prec]
+    assert _walls_zero(gotA)
+
+
+@pytest.mark.parametrize("prec,order,kblock,n,periods", [("fp64", 2, 3, (70, 37, 29), 2), ("fp64", 4, 2, (3, 4, 5), 2),
+                                                         ("fp32", 2, 4, (65, 40, 21), 1),
+                                                         ("fp32", 4, 3, (47, 30, 50), 1)])
+def test_3d_blocked_constant_c_and_final_state(torch, prec, order, kblock, n, periods):
+    """Constant c^2, a grid smaller than the halo, two periods: the filtered
+    result and the final wave state against the oracle."""
+    _say(f"[3d blocked const] {prec} p={order} K={kblock} n={n}")
+    grid = oc.Grid(3, n, order)
+    f = wl.random_field(grid.shape, seed=641)
+    v = wl.random_field(grid.shape, seed=642)
+    s = _solver(3, n, order, prec)
+    s.set_tuning("blocked_3d", kblock, 0)
+    s.set_c2(1.3)
+    s.set_source(f)
+    s.set_frequency(9.0, periods=periods)
+    tp = oc.time_params(grid, 1.3, 9.0, periods=periods)
+    fin, fil = s.run_periods(_to_dev(torch, v), with_forcing=True)
+    want_fil, want_fin = oc.apply(grid, 1.3, f, v, tp, return_final=True)
+    assert _err(prec, fil.cpu().numpy(), want_fil, v) <= TOL[prec]
+    assert _err(prec, fin.cpu().numpy(), want_fin, v) <= TOL[prec]
+    assert _walls_zero(fin.cpu().numpy())
+
+
+def test_3d_blocked_unsupported_tunings(torch):
+    from paper_2504_03074_amd import WhError
+    _say("[3d blocked errors]")
+    s = _solver(3, (20, 20, 20), 4, "fp64")
+    for kblock, rows in [(3, 32), (4, 16), (5, 0), (0, 0), (2, 24), (2, 64)]:
+        with pytest.raises(WhError):
+            s.set_tuning("blocked_3d", kblock, rows)
+    s2 = _solver(2, (20, 20), 2, "fp64")
+    with pytest.raises(WhError):
+        s2.set_tuning("blocked_3d", 2, 0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_autotune_keeps_results(torch, prec):
     _say(f"[autotune] {prec}")
