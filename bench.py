@@ -21,7 +21,9 @@ per launch over its event-timed average duration against 8 TB/s HBM), and the
 CPU oracle's rate on a bounded sample of the same workload.
 
 Other modes (used to produce the committed rocprofv3 summaries):
-  --mode kernel   only W_h applications (A v) of the workload, no solver
+  --mode kernel   only W_h applications (A v) of the workload, no solver;
+                  with --workload cube: the 512^3 cube (c = 1 with a c = 1.5
+                  ball, omega = 80, point-like source, 2nd order, FP32 state)
   --mode copy     a plain device copy of known size (HBM counter calibration)
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
@@ -50,8 +52,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before timing")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--n", type=int, default=2048, help="cells per axis")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="state precision (default: fp64 for the square, fp32 for the cube)")
+    ap.add_argument("--workload", choices=["square", "cube"], default="square",
+                    help="square: 2048^2 random c^2 (default); cube: 512^3 inclusion, --mode kernel only")
+    ap.add_argument("--order", type=int, choices=[2, 4], default=0, help="stencil order (default: 4 square, 2 cube)")
+    ap.add_argument("--n", type=int, default=0, help="cells per axis (default: 2048 square, 512 cube)")
     ap.add_argument("--solver", choices=["cg", "gmres"], default="cg")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -67,7 +73,58 @@ def parse():
     ap.add_argument("--applies", type=int, default=20, help="applications timed in --mode kernel")
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
-    return ap.parse_args()
+    args = ap.parse_args()
+    cube = args.workload == "cube"
+    if args.precision is None:
+        args.precision = "fp32" if cube else "fp64"
+    if not args.order:
+        args.order = 2 if cube else 4
+    if not args.n:
+        args.n = 512 if cube else 2048
+    if cube and args.mode != "kernel":
+        ap.error("--workload cube is measured with --mode kernel")
+    return args
+
+
+def run_cube_kernel(args, dev):
+    """The 512^3 cube (c = 1 with a c = 1.5 ball, omega = 80, point-like
+    source): A v applications only, timed with events on the library's
+    stream."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    n = args.n
+    w = wl.cube_inclusion(n=n, order=args.order)
+    s = Solver(3, (n, n, n), order=args.order, precision=args.precision)
+    s.set_tuning(args.kernel, args.kblock, args.tile)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    tp = s.set_frequency(w["omega"])
+    del w
+    tun = s.tuning()
+    log(f"cube {n}^3 p={args.order} {args.precision}: time params {tp}, tuning {tun}")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    v = torch.randn(s.shape, dtype=torch.float64, device=dev, generator=g)
+    out = s.new()
+    for _ in range(2):
+        s.apply_A(v, out=out)
+    torch.cuda.synchronize()
+    s.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.applies):
+        s.apply_A(v, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pr = s.profile_read()
+    s.profile_enable(False)
+    print(json.dumps({"mode": "kernel", "workload": f"cube {n}^3, order {args.order}, c = 1 with a c = 1.5 ball, "
+                      f"omega = {tp['omega']}", "precision": args.precision, "kernel": tun["kernel"],
+                      "kblock": tun["kblock"], "tile": tun["tile"], "nt": tp["nt"], "applies": args.applies,
+                      "ms_per_apply": dt / args.applies * 1e3, "launches": pr["launches"],
+                      "us_per_launch": pr["ms"] / pr["launches"] * 1e3,
+                      "alg_GBps": pr["bytes"] / pr["ms"] * 1e-6,
+                      "GPts_per_s": pr["point_steps"] / pr["ms"] * 1e-6}), flush=True)
 
 
 def log(msg):
@@ -385,8 +442,11 @@ def main():
     if args.mode == "adjoint":
         run_adjoint(args, dev)
         return
+    if args.workload == "cube":
+        run_cube_kernel(args, dev)
+        return
 
-    order = 4
+    order = args.order
     t_setup = time.perf_counter()
     w = wl.smooth_random_speed_sources(n=args.n, order=order)
     log(f"inputs generated in {time.perf_counter() - t_setup:.1f}s")
@@ -476,7 +536,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-state/f64-acc",
         "data": "synthetic (seeded random c^2 and Gaussian sources)",
         "config": {
-            "workload": f"square {args.n}^2, 4th order, random c^2 in [0.5,2], omega=200, 4 Gaussian sources, "
+            "workload": f"square {args.n}^2, order {order}, random c^2 in [0.5,2], omega=200, 4 Gaussian sources, "
                         + (f"GMRES({args.restart})" if args.solver == "gmres" else "CG (1/c^2 inner product)")
                         + f" to {args.rtol:g}",
             "n": args.n, "order": order, "omega": w["omega"], "nt": tp["nt"], "solver": args.solver,
