@@ -374,6 +374,47 @@ WH_API wh_status wh_deflation_workspace_size(wh_ctx *ctx, int32_t count, size_t 
 WH_API wh_status wh_set_deflation(wh_ctx *ctx, const int32_t *modes, int32_t count, void *workspace, size_t bytes);
 
 /* ------------------------------------------------------------------------
+ * Implicit time stepping (Sec. 4.2.2, eq. WaveSchemeImplicit), 2-D grids,
+ * FP64-state contexts.
+ *
+ * Each step solves the trapezoidal-in-time scheme
+ *   M W^{n+1} = 2 W^n - M W^{n-1} - dt^2 cos(omega_i t^n) cos(omega_i dt) f,
+ *   M = I - (dt^2/2) c^2 Delta_{h,p},
+ * and the first step M W^1 = W^0 - (dt^2/2) cos(omega_i dt) f (the zero
+ * initial velocity eliminates W^{-1}).  The time step follows the implicit
+ * correction recipe (Appendix A.2): N_t = nits >= 5 steps per period,
+ * dt = sqrt(2 / cos(2 pi / N_t) - 2) / omega, omega_i = 2 pi / (N_t dt)
+ * (returned as omega_e by wh_get_time_params); the filter is the explicit
+ * scheme's with omega_i.  The library solves each step in the symmetric form
+ * (1/c^2) M X = (1/c^2) R by conjugate gradients preconditioned with one
+ * geometric multigrid V-cycle (damped Jacobi, full weighting, bilinear
+ * interpolation, 2nd-order coarse operators; levels halve the grid while
+ * both axes have an even number of cells), to a relative residual of
+ * inner_rtol.  Every solver (FPI, GMRES, CG, deflation) then uses these
+ * applications; the batched solve, the adjoint and the autotuner do not.
+ * ---------------------------------------------------------------------- */
+
+/* Switch the context to implicit stepping with nits (>= 5) steps per period
+ * and inner tolerance inner_rtol (0 < inner_rtol <= 1e-2), or back to
+ * explicit stepping with nits = 0.  Clears the frequency and deflation
+ * (call wh_set_frequency again).  WH_EINVAL for 3-D grids or FP32 state. */
+WH_API wh_status wh_set_implicit(wh_ctx *ctx, int32_t nits, double inner_rtol);
+
+/* Bytes of the caller-owned implicit workspace for the current grid (the
+ * multigrid hierarchy and the inner CG vectors: about 7.4 FP64 node arrays). */
+WH_API wh_status wh_implicit_workspace_size(const wh_ctx *ctx, size_t *bytes);
+
+/* Bind (or, with NULL, unbind) the implicit workspace (256-byte aligned
+ * device memory of at least wh_implicit_workspace_size bytes). */
+WH_API wh_status wh_bind_implicit_workspace(wh_ctx *ctx, void *ptr, size_t bytes);
+
+/* Counters of the implicit steps taken since the grid was set: steps, inner
+ * CG iterations in total and at most per step, and multigrid levels
+ * (nullable outputs). */
+WH_API wh_status wh_implicit_stats(const wh_ctx *ctx, int64_t *steps, int64_t *inner_iters, int32_t *max_inner,
+                                   int32_t *levels);
+
+/* ------------------------------------------------------------------------
  * Discrete adjoint (FP64-state contexts).
  *
  * One application Y = W_h(v, f) (the explicit scheme of Sec. 4.2.1 and the

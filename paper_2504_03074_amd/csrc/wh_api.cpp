@@ -58,6 +58,26 @@ struct wh_ctx {
   double *pinned = nullptr;  // host staging for reduction results
   size_t pinned_count = 0;
 
+  // implicit time stepping (2-D, FP64 state): steps per period, tolerance of
+  // the inner solves, and the multigrid hierarchy held in the caller's
+  // implicit workspace
+  bool implicit = false;
+  int nits = 10;
+  double imp_rtol = 1e-12;
+  char *imp = nullptr;
+  size_t imp_bytes = 0;
+  struct MgLevel {
+    wh::MgGeom g;
+    double *d, *x, *b, *t;  // 1/c^2, solution, right-hand side, smoother buffer
+  };
+  std::vector<MgLevel> mg;
+  double dconst = 1.0;  // 1/c^2 when c^2 is constant (d == nullptr)
+  bool mg_ready = false;
+  double *imp_r = nullptr, *imp_z = nullptr, *imp_p = nullptr, *imp_q = nullptr;
+  double *imp_part = nullptr, *imp_scal = nullptr;
+  int64_t imp_steps = 0, imp_iters = 0;
+  int imp_max = 0;
+
   struct Timed {
     hipEvent_t a, b;
     int64_t launches;
@@ -337,9 +357,243 @@ bool tuning_supported(const wh_ctx *c, int kernel, int kblock, int tile) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// implicit time stepping (Sec. 4.2.2): multigrid-preconditioned CG per step
+// ---------------------------------------------------------------------------
+constexpr int kMgPreSweeps = 2;     // = post-sweeps (symmetric V-cycle)
+constexpr int kMgCoarseSweeps = 20;  // even: the result ends in x
+constexpr int kImpMaxInner = 500;
+
+// Grid sizes of the multigrid levels: halve while both axes are even and the
+// coarse grid keeps at least two cells per axis.
+std::vector<std::pair<int, int>> mg_shapes(const wh_ctx *c) {
+  std::vector<std::pair<int, int>> out;
+  int nx = (int)c->n[0], ny = (int)c->n[1];
+  out.push_back({nx, ny});
+  while (nx % 2 == 0 && ny % 2 == 0 && nx >= 4 && ny >= 4) {
+    nx /= 2;
+    ny /= 2;
+    out.push_back({nx, ny});
+  }
+  return out;
+}
+
+struct ImpLayout {
+  size_t total = 0;
+  std::vector<size_t> off;  // level 0: d, t, r, z, p, q; level l >= 1: d, x, b, t; then partials, scalars
+};
+
+ImpLayout imp_layout(const wh_ctx *c) {
+  ImpLayout L;
+  auto seg = [&](size_t bytes) {
+    L.off.push_back(L.total);
+    L.total += (bytes + 255) / 256 * 256;
+  };
+  const auto shapes = mg_shapes(c);
+  for (size_t l = 0; l < shapes.size(); ++l) {
+    const size_t nodes = (size_t)(shapes[l].first + 1) * (size_t)(shapes[l].second + 1);
+    for (int a = 0; a < (l == 0 ? 6 : 4); ++a) seg(nodes * 8);
+  }
+  seg((size_t)wh::reduction_blocks(c->nodes) * 8);
+  seg(16 * 8);
+  return L;
+}
+
+// Level geometry for theta = dt^2 / 2 (fine level: order p; coarse: order 2).
+wh::MgGeom mg_geom(int nx, int ny, int order, double theta) {
+  wh::MgGeom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.sy = nx + 1;
+  g.nodes = (int64_t)(nx + 1) * (ny + 1);
+  g.order = order;
+  const double div = order == 4 ? 12.0 : 1.0;
+  g.ax = theta * (double)nx * nx / div;
+  g.ay = theta * (double)ny * ny / div;
+  g.ac = (order == 4 ? 30.0 : 2.0) * (g.ax + g.ay);
+  return g;
+}
+
+wh_status mg_setup(wh_ctx *c) {
+  if (!c->imp) return fail(c, WH_ESTATE, "implicit stepping needs its workspace (wh_bind_implicit_workspace)");
+  const ImpLayout L = imp_layout(c);
+  const auto shapes = mg_shapes(c);
+  const double theta = 0.5 * c->tp.dt * c->tp.dt;
+  auto at = [&](size_t k) { return reinterpret_cast<double *>(c->imp + L.off[k]); };
+  c->mg.clear();
+  size_t k = 0;
+  const bool cvar = !c->c2_is_const;
+  c->dconst = 1.0 / c->c2_value;
+  for (size_t l = 0; l < shapes.size(); ++l) {
+    wh_ctx::MgLevel lev{};
+    lev.g = mg_geom(shapes[l].first, shapes[l].second, l == 0 ? c->order : 2, theta);
+    if (l == 0) {
+      lev.d = at(k);
+      lev.t = at(k + 1);
+      c->imp_r = at(k + 2);
+      c->imp_z = at(k + 3);
+      c->imp_p = at(k + 4);
+      c->imp_q = at(k + 5);
+      lev.b = c->imp_r;
+      lev.x = c->imp_z;
+      k += 6;
+    } else {
+      lev.d = at(k);
+      lev.x = at(k + 1);
+      lev.b = at(k + 2);
+      lev.t = at(k + 3);
+      k += 4;
+    }
+    if (!cvar) lev.d = nullptr;
+    c->mg.push_back(lev);
+  }
+  c->imp_part = at(k);
+  c->imp_scal = at(k + 1);
+  if (cvar) {
+    WH_HIP(c, wh::launch_mg_inverse(c->mg[0].g, static_cast<const double *>(c->c2), c->mg[0].d, c->stream));
+    for (size_t l = 1; l < c->mg.size(); ++l)
+      WH_HIP(c, wh::launch_mg_inject(c->mg[l - 1].g, c->mg[l - 1].d, c->mg[l].g, c->mg[l].d, c->stream));
+  }
+  c->mg_ready = true;
+  return WH_OK;
+}
+
+// x_l = V-cycle approximation of S_l^{-1} b_l (x_l starts from 0).
+wh_status mg_vcycle(wh_ctx *c, size_t l) {
+  wh_ctx::MgLevel &L = c->mg[l];
+  const double w = L.g.order == 4 ? 0.75 : 0.8;
+  const int sweeps = l + 1 == c->mg.size() ? kMgCoarseSweeps : kMgPreSweeps;
+  // damped Jacobi from x = 0, ping-ponging between t and x (even count: ends in x)
+  WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, nullptr, L.b, L.t, w, c->stream));
+  for (int sw = 1; sw < sweeps; ++sw) {
+    const bool to_x = (sw & 1) != 0;
+    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_x ? L.t : L.x, L.b, to_x ? L.x : L.t, w, c->stream));
+  }
+  if (l + 1 == c->mg.size()) return WH_OK;
+  wh_ctx::MgLevel &C = c->mg[l + 1];
+  WH_HIP(c, wh::launch_mg_residual(L.g, L.d, c->dconst, L.x, L.b, L.t, c->stream));
+  WH_HIP(c, wh::launch_mg_restrict(L.g, L.t, C.g, C.b, c->stream));
+  WH_TRY(mg_vcycle(c, l + 1));
+  WH_HIP(c, wh::launch_mg_prolong(C.g, C.x, L.g, L.x, c->stream));
+  for (int sw = 0; sw < kMgPreSweeps; ++sw) {
+    const bool to_t = (sw & 1) == 0;
+    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_t ? L.x : L.t, L.b, to_t ? L.t : L.x, w, c->stream));
+  }
+  return WH_OK;
+}
+
+wh_status imp_dot(wh_ctx *c, const double *x, const double *y, int slot) {
+  const int nb = wh::reduction_blocks(c->nodes);
+  WH_HIP(c, wh::launch_mdot(x, 0, 1, y, c->nodes, c->imp_part, nb, c->stream));
+  WH_HIP(c, wh::launch_reduce_rows(c->imp_part, nb, 1, c->imp_scal + slot, c->stream));
+  return WH_OK;
+}
+
+wh_status imp_fetch(wh_ctx *c, int slot, double *out) {
+  WH_HIP(c, hipMemcpyAsync(c->pinned, c->imp_scal + slot, 8, hipMemcpyDeviceToHost, c->stream));
+  WH_HIP(c, hipStreamSynchronize(c->stream));
+  *out = c->pinned[0];
+  return WH_OK;
+}
+
+// Solve S x = B (B in imp_q, x holds the initial guess) by CG preconditioned
+// with one V-cycle, to ||B - S x|| <= imp_rtol ||B||.
+wh_status pcg_solve(wh_ctx *c, double *x) {
+  const wh::MgGeom &g = c->mg[0].g;
+  const double *d = c->mg[0].d;
+  const int64_t N = c->nodes;
+  double *r = c->imp_r, *z = c->imp_z, *p = c->imp_p, *q = c->imp_q;
+  double bb = 0.0, rr = 0.0;
+  WH_TRY(imp_dot(c, q, q, 4));
+  WH_TRY(imp_fetch(c, 4, &bb));
+  if (!std::isfinite(bb)) return fail(c, WH_ENONFINITE, "implicit step: right-hand side is not finite");
+  if (bb == 0.0) {
+    WH_HIP(c, wh::launch_fill(x, 0.0, N, c->stream));
+    return WH_OK;
+  }
+  const double tol2 = c->imp_rtol * c->imp_rtol * bb;
+  WH_HIP(c, wh::launch_mg_residual(g, d, c->dconst, x, q, r, c->stream));
+  WH_TRY(imp_dot(c, r, r, 2));
+  WH_TRY(imp_fetch(c, 2, &rr));
+  int it = 0;
+  if (rr > tol2) {
+    WH_TRY(mg_vcycle(c, 0));  // z = B_mg r
+    WH_TRY(imp_dot(c, r, z, 0));
+    WH_HIP(c, wh::launch_pcg_xpay(N, z, p, nullptr, nullptr, c->stream));
+    while (true) {
+      WH_HIP(c, wh::launch_mg_residual(g, d, c->dconst, p, nullptr, q, c->stream));  // q = S p
+      WH_TRY(imp_dot(c, p, q, 1));
+      WH_HIP(c, wh::launch_pcg_update(N, x, r, p, q, c->imp_scal + 0, c->imp_scal + 1, c->stream));
+      WH_TRY(imp_dot(c, r, r, 2));
+      WH_TRY(imp_fetch(c, 2, &rr));
+      ++it;
+      if (!std::isfinite(rr)) return fail(c, WH_ENONFINITE, "implicit step: inner CG became non-finite");
+      if (rr <= tol2) break;
+      if (it >= kImpMaxInner)
+        return fail(c, WH_ENOTCONV, "implicit step: inner CG did not reach %g in %d iterations (at %g)",
+                    c->imp_rtol, it, std::sqrt(rr / bb));
+      WH_TRY(mg_vcycle(c, 0));
+      WH_TRY(imp_dot(c, r, z, 3));
+      WH_HIP(c, wh::launch_pcg_xpay(N, z, p, c->imp_scal + 3, c->imp_scal + 0, c->stream));
+      WH_HIP(c, hipMemcpyAsync(c->imp_scal + 0, c->imp_scal + 3, 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+  }
+  c->imp_steps += 1;
+  c->imp_iters += it;
+  c->imp_max = std::max(c->imp_max, it);
+  return WH_OK;
+}
+
+// One WaveHoltz application with implicit steps (eq. WaveSchemeImplicit):
+// M W^1 = W^0 - (dt^2/2) cos(omega_i dt) f (the initial condition eliminates
+// W^{-1}), then M W^{n+1} = 2 W^n - M W^{n-1} - dt^2 cos(omega_i t^n)
+// cos(omega_i dt) f, each solved in the symmetric form by pcg_solve.
+wh_status apply_implicit(wh_ctx *c, const double *v, bool forcing, int mode, double *out, double *w_final) {
+  if (!c->mg_ready) WH_TRY(mg_setup(c));
+  const int64_t nt = c->tp.nt, N = nt * (int64_t)c->tp.periods;
+  const double dt = c->tp.dt, cw = std::cos(c->tp.omega_e * dt);
+  const wh::MgGeom &g = c->mg[0].g;
+  const double *d = c->mg[0].d;
+  const double *f = forcing ? static_cast<const double *>(c->f) : nullptr;
+  double *lv[3] = {static_cast<double *>(c->W[0]), static_cast<double *>(c->W[1]), static_cast<double *>(c->W[2])};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->profiling) {
+    WH_TRY(take_events(c, &ev0, &ev1));
+    WH_HIP(c, hipEventRecord(ev0, c->stream));
+  }
+  // W^0 = v with the walls set to 0
+  WH_HIP(c, hipMemcpyAsync(lv[0], v, (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  WH_HIP(c, wh::launch_set_walls(false, geometry(c, 1.0), lv[0], 0.0, c->stream));
+  WH_HIP(c, wh::launch_imp_rhs(g, d, c->dconst, lv[0], nullptr, f, -0.5 * dt * dt * cw, c->imp_q, lv[1], c->stream));
+  WH_TRY(pcg_solve(c, lv[1]));
+  WH_HIP(c, wh::launch_imp_filter(g, lv[0], c->wts[0], c->acc, true, wh::ACCUMULATE, v, out, c->stream));
+  WH_HIP(c, wh::launch_imp_filter(g, lv[1], c->wts[1], c->acc, false, N == 1 ? mode : wh::ACCUMULATE, v, out,
+                                  c->stream));
+  int prev = 0, cur = 1, nxt = 2;
+  for (int64_t n = 1; n < N; ++n) {
+    const double gn = -dt * dt * std::cos(2.0 * M_PI * (double)(n % nt) / (double)nt) * cw;
+    WH_HIP(c, wh::launch_imp_rhs(g, d, c->dconst, lv[cur], lv[prev], f, gn, c->imp_q, lv[nxt], c->stream));
+    WH_TRY(pcg_solve(c, lv[nxt]));
+    WH_HIP(c, wh::launch_imp_filter(g, lv[nxt], c->wts[(size_t)n + 1], c->acc, false,
+                                    n == N - 1 ? mode : wh::ACCUMULATE, v, out, c->stream));
+    const int t = prev;
+    prev = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (c->profiling) {
+    WH_HIP(c, hipEventRecord(ev1, c->stream));
+    c->pending.push_back({ev0, ev1, N, 0.0, interior_nodes(c) * (double)N});
+    if (c->pending.size() >= 256) WH_TRY(drain_profile(c));
+  }
+  if (w_final) WH_HIP(c, hipMemcpyAsync(w_final, lv[cur], (size_t)c->nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  return WH_OK;
+}
+
 // One WaveHoltz application.  mode: ACCUMULATE (acc keeps the filter),
 // FINAL_FILTER (out = filtered) or FINAL_A (out = v - filtered).
 wh_status apply_impl(wh_ctx *c, const double *v, bool forcing, int mode, double *out, double *w_final) {
+  if (c->implicit) return apply_implicit(c, v, forcing, mode, out, w_final);
   const bool fp32 = c->prec == WH_FP32_STATE;
   const int64_t N = (int64_t)c->tp.nt * c->tp.periods;
   const double dt2 = c->tp.dt * c->tp.dt;
@@ -449,9 +703,15 @@ double axis_eigenvalue(int order, int64_t n, int64_t k) {
 double mode_beta(const wh_ctx *c, double lam2) {
   const double dt = c->tp.dt, we = c->tp.omega_e, al = c->tp.alpha;
   const double Tbar = (double)c->tp.nt * c->tp.periods * dt;
-  const double arg = 0.5 * std::sqrt(lam2) * dt;
-  if (arg >= 1.0) return NAN;
-  const double lt = (2.0 / dt) * std::asin(arg);
+  double lt;
+  if (c->implicit) {
+    // mode map of the implicit scheme, eq. (lambdaTildeImplicit)
+    lt = std::acos(1.0 / (1.0 + 0.5 * lam2 * dt * dt)) / dt;
+  } else {
+    const double arg = 0.5 * std::sqrt(lam2) * dt;
+    if (arg >= 1.0) return NAN;
+    lt = (2.0 / dt) * std::asin(arg);  // eq. (discreteExplicitLambdaTilde)
+  }
   return sincd(we + lt, Tbar, dt) + sincd(we - lt, Tbar, dt) - al * sincd(lt, Tbar, dt);
 }
 
@@ -645,6 +905,10 @@ wh_status wh_set_grid(wh_ctx *c, int32_t dim, const int64_t n[3], int32_t order,
   c->adj = nullptr;
   c->adj_bytes = 0;
   c->defl_count = 0;
+  c->implicit = false;
+  c->imp = nullptr;
+  c->imp_bytes = 0;
+  c->mg_ready = false;
   c->err.clear();
   return WH_OK;
 }
@@ -758,6 +1022,32 @@ wh_status wh_set_source(wh_ctx *c, const double *f, int32_t on_device) {
 wh_status wh_set_frequency(wh_ctx *c, double omega, int32_t periods, double cfl_frac, int32_t nt_override,
                            double alpha) {
   WH_TRY(need(c, true, true, true, false, false));
+  if (c->implicit) {
+    // implicit time-stepping correction recipe (Appendix A.2): N_t steps per
+    // period, dt = sqrt(2 / cos(2 pi / N_t) - 2) / omega, omega_i = 2 pi / (N_t dt)
+    if (!(omega > 0.0) || !std::isfinite(omega) || periods < 1 || periods > 10000)
+      return fail(c, WH_EINVAL, "invalid frequency parameters (omega %g, periods %d)", omega, periods);
+    if (nt_override != 0 && nt_override != c->nits)
+      return fail(c, WH_EINVAL, "with implicit stepping the steps per period are set by wh_set_implicit");
+    const int nt = c->nits;
+    wh_time_params tp{};
+    tp.nt = nt;
+    tp.periods = periods;
+    tp.omega = omega;
+    tp.dt = std::sqrt(2.0 / std::cos(2.0 * M_PI / nt) - 2.0) / omega;
+    tp.omega_e = 2.0 * M_PI / (nt * tp.dt);
+    const double alpha_d = std::tan(M_PI / nt) / std::tan(2.0 * M_PI / nt);
+    tp.alpha = alpha < 0.0 ? alpha_d : alpha;
+    double s2 = 0.0;
+    for (int m = 0; m < c->dim; ++m) s2 += (double)c->n[m] * (double)c->n[m];
+    tp.cfl = std::sqrt(c->c2max) * tp.dt * std::sqrt(s2);
+    tp.c2max = c->c2max;
+    c->tp = tp;
+    build_tables(c);
+    c->freq_set = true;
+    c->mg_ready = false;
+    return c->imp ? mg_setup(c) : WH_OK;
+  }
   wh_time_params tp{};
   const wh_status st =
       wh_compute_time_params(c->dim, c->n, c->order, c->c2max, omega, periods, cfl_frac, nt_override, alpha, &tp);
@@ -878,6 +1168,7 @@ wh_status wh_get_tuning(const wh_ctx *c, int32_t *kernel, int32_t *kblock, int32
 wh_status wh_autotune(wh_ctx *c, int32_t applies, int32_t *kernel, int32_t *kblock, int32_t *tile,
                       double *ms_per_apply) {
   WH_TRY(need(c, true, true, true, false, true));
+  if (c->implicit) return fail(c, WH_EINVAL, "the autotuner chooses among explicit stepping kernels");
   if (applies < 1 || applies > 100) return fail(c, WH_EINVAL, "applies must be in 1..100");
   WH_TRY(set_device(c));
   std::vector<Tuning> cands{{WH_KERNEL_NODE, 1, 0}};
@@ -1593,12 +1884,74 @@ AdjLayout adjoint_layout(const wh_ctx *c) {
 
 wh_status need_fp64(wh_ctx *c, const char *what) {
   if (c->prec != WH_FP64) return fail(c, WH_EINVAL, "%s needs an FP64-state context", what);
+  if (c->implicit) return fail(c, WH_EINVAL, "%s is built for explicit time stepping", what);
   return WH_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+wh_status wh_set_implicit(wh_ctx *c, int32_t nits, double inner_rtol) {
+  WH_TRY(need(c, true, false, false, false, false));
+  if (nits == 0) {
+    c->implicit = false;
+    c->freq_set = false;
+    c->mg_ready = false;
+    return WH_OK;
+  }
+  if (c->dim != 2) return fail(c, WH_EINVAL, "implicit time stepping is built for 2-D grids");
+  if (c->prec != WH_FP64) return fail(c, WH_EINVAL, "implicit time stepping needs an FP64-state context");
+  if (nits < 5 || nits > 100000)
+    return fail(c, WH_EINVAL, "implicit stepping needs 5 <= steps per period <= 100000 (got %d)", nits);
+  if (!(inner_rtol > 0.0) || inner_rtol > 1e-2)
+    return fail(c, WH_EINVAL, "inner tolerance must be in (0, 1e-2] (got %g)", inner_rtol);
+  c->implicit = true;
+  c->nits = nits;
+  c->imp_rtol = inner_rtol;
+  c->freq_set = false;
+  c->mg_ready = false;
+  c->defl_count = 0;
+  return WH_OK;
+}
+
+wh_status wh_implicit_workspace_size(const wh_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return WH_EINVAL;
+  if (!c->grid_set) return WH_ESTATE;
+  *bytes = imp_layout(c).total;
+  return WH_OK;
+}
+
+wh_status wh_bind_implicit_workspace(wh_ctx *c, void *ptr, size_t bytes) {
+  WH_TRY(need(c, true, false, false, false, false));
+  c->mg_ready = false;
+  if (!ptr) {
+    c->imp = nullptr;
+    c->imp_bytes = 0;
+    return WH_OK;
+  }
+  if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+    return fail(c, WH_EINVAL, "implicit workspace must be 256-byte aligned");
+  const size_t need_bytes = imp_layout(c).total;
+  if (bytes < need_bytes)
+    return fail(c, WH_ENOMEM, "implicit workspace too small: %zu bytes given, %zu needed", bytes, need_bytes);
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, ptr, "implicit workspace"));
+  c->imp = static_cast<char *>(ptr);
+  c->imp_bytes = bytes;
+  if (c->implicit && c->freq_set) return mg_setup(c);
+  return WH_OK;
+}
+
+wh_status wh_implicit_stats(const wh_ctx *c, int64_t *steps, int64_t *inner_iters, int32_t *max_inner,
+                            int32_t *levels) {
+  if (!c) return WH_EINVAL;
+  if (steps) *steps = c->imp_steps;
+  if (inner_iters) *inner_iters = c->imp_iters;
+  if (max_inner) *max_inner = c->imp_max;
+  if (levels) *levels = c->grid_set ? (int32_t)mg_shapes(c).size() : 0;
+  return WH_OK;
+}
 
 wh_status wh_adjoint_workspace_size(wh_ctx *c, size_t *bytes) {
   WH_TRY(need(c, true, false, false, false, true));
@@ -2087,6 +2440,7 @@ wh_status wh_batch_add(wh_batch *b, wh_ctx *c, int32_t *index) {
   if ((int)b->probs.size() >= WH_MAX_BATCH) return bfail(b, WH_EINVAL, "at most %d problems per batch", WH_MAX_BATCH);
   if (!c->grid_set || !c->ws || !c->c2_set || !c->f_set || !c->freq_set)
     return bfail(b, WH_ESTATE, "problem must have grid, workspace, c^2, source and frequency set");
+  if (c->implicit) return bfail(b, WH_EINVAL, "the batched solve uses explicit time stepping");
   if (c->dim != 2) return bfail(b, WH_EINVAL, "batches hold 2-D problems");
   if (c->defl_count > 0) return bfail(b, WH_EINVAL, "problems with deflation set cannot be batched");
   if (c->ws_restart < 2) return bfail(b, WH_ENOMEM, "problem workspace must be sized for restart >= 2");

@@ -83,6 +83,34 @@ hipError_t launch_step3d_zcol(bool fp32, const StepGeom &g, int zb, const void *
 bool zcol_supported(int zb);
 
 // ---------------------------------------------------------------------------
+// Implicit time stepping on 2-D grids (FP64): one multigrid level of the
+// symmetric step operator S x = (d + ac) x - ax S_x(x) - ay S_y(x), d = 1/c^2.
+// ---------------------------------------------------------------------------
+struct MgGeom {
+  int nx, ny;       // cells per axis
+  int64_t sy;       // row stride (nx + 1)
+  int64_t nodes;    // (nx + 1)(ny + 1)
+  int order;        // 2 or 4 (coarse levels: 2)
+  double ax, ay, ac;
+};
+hipError_t launch_mg_smooth(const MgGeom &g, const double *dinv, double dconst, const double *x_in,
+                            const double *b, double *x_out, double w, hipStream_t s);
+hipError_t launch_mg_residual(const MgGeom &g, const double *dinv, double dconst, const double *x, const double *b,
+                              double *r, hipStream_t s);
+hipError_t launch_mg_restrict(const MgGeom &gf, const double *rf, const MgGeom &gc, double *bc, hipStream_t s);
+hipError_t launch_mg_prolong(const MgGeom &gc, const double *xc, const MgGeom &gf, double *xf, hipStream_t s);
+hipError_t launch_mg_inject(const MgGeom &gf, const double *df, const MgGeom &gc, double *dc, hipStream_t s);
+hipError_t launch_mg_inverse(const MgGeom &g, const double *c2, double *d, hipStream_t s);
+hipError_t launch_imp_rhs(const MgGeom &g, const double *dinv, double dconst, const double *cur, const double *prev,
+                          const double *f, double gn, double *B, double *X0, hipStream_t s);
+hipError_t launch_imp_filter(const MgGeom &g, const double *x, double w, double *acc, bool init, int mode,
+                             const double *v, double *out, hipStream_t s);
+hipError_t launch_pcg_update(int64_t n, double *x, double *r, const double *p, const double *q, const double *num,
+                             const double *den, hipStream_t s);
+hipError_t launch_pcg_xpay(int64_t n, const double *z, double *p, const double *num, const double *den,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Batches of independent 2-D problems (same order and precision).
 // ---------------------------------------------------------------------------
 // One problem of a batched blocked pass (device-resident table).

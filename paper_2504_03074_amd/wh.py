@@ -119,6 +119,11 @@ def _load():
                                      ctypes.POINTER(ctypes.c_double)]),
         "wh_deflation_workspace_size": (st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
         "wh_set_deflation": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _vp, ctypes.c_size_t]),
+        "wh_set_implicit": (st, [_vp, ctypes.c_int32, ctypes.c_double]),
+        "wh_implicit_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "wh_bind_implicit_workspace": (st, [_vp, _vp, ctypes.c_size_t]),
+        "wh_implicit_stats": (st, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "wh_adjoint_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "wh_bind_adjoint_workspace": (st, [_vp, _vp, ctypes.c_size_t]),
         "wh_gradient": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -354,6 +359,28 @@ def wh_set_deflation(ctx, modes, ptr, nbytes):
     dim = len(modes[0]) if modes else 1
     arr = (ctypes.c_int32 * max(len(modes) * dim, 1))(*[int(k) for m in modes for k in m])
     _check(ctx, _load().wh_set_deflation(ctx, arr, len(modes), _vp(ptr) if ptr else None, int(nbytes)))
+
+
+def wh_set_implicit(ctx, nits: int, inner_rtol: float):
+    _check(ctx, _load().wh_set_implicit(ctx, int(nits), float(inner_rtol)))
+
+
+def wh_implicit_workspace_size(ctx) -> int:
+    out = ctypes.c_size_t()
+    _check(ctx, _load().wh_implicit_workspace_size(ctx, ctypes.byref(out)))
+    return out.value
+
+
+def wh_bind_implicit_workspace(ctx, ptr, nbytes):
+    _check(ctx, _load().wh_bind_implicit_workspace(ctx, _vp(ptr) if ptr else None, int(nbytes)))
+
+
+def wh_implicit_stats(ctx) -> dict:
+    steps, iters = ctypes.c_int64(), ctypes.c_int64()
+    mx, lv = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, _load().wh_implicit_stats(ctx, ctypes.byref(steps), ctypes.byref(iters), ctypes.byref(mx),
+                                          ctypes.byref(lv)))
+    return dict(steps=steps.value, inner_iters=iters.value, max_inner=mx.value, levels=lv.value)
 
 
 def wh_adjoint_workspace_size(ctx) -> int:
@@ -628,6 +655,25 @@ class Solver:
         self._defl_ws = self._torch.empty(need, dtype=self._torch.uint8, device=self.device)
         wh_set_deflation(self.ctx, modes, self._defl_ws.data_ptr(), need)
         return modes, mu
+
+    # ---- implicit time stepping (2-D, FP64 state) ----
+    def set_implicit(self, nits=10, rtol=1e-12):
+        """Implicit steps (nits >= 5 per period, multigrid-preconditioned CG to
+        rtol per step), or explicit again with nits = 0.  Call set_frequency
+        afterwards."""
+        wh_set_implicit(self.ctx, nits, rtol)
+        if nits == 0:
+            wh_bind_implicit_workspace(self.ctx, None, 0)
+            self._imp_ws = None
+            return
+        need = wh_implicit_workspace_size(self.ctx)
+        ws = getattr(self, "_imp_ws", None)
+        if ws is None or ws.numel() < need:
+            self._imp_ws = self._torch.empty(need, dtype=self._torch.uint8, device=self.device)
+        wh_bind_implicit_workspace(self.ctx, self._imp_ws.data_ptr(), self._imp_ws.numel())
+
+    def implicit_stats(self):
+        return wh_implicit_stats(self.ctx)
 
     # ---- discrete adjoint (FP64 state) ----
     def _adjoint_ready(self):
