@@ -28,6 +28,11 @@ Other modes (used to produce the committed rocprofv3 summaries):
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
                   by the batched CG, against solving them one at a time
+  --mode implicit implicit stepping (N_ITS steps per period, multigrid-
+                  preconditioned CG per step) against explicit stepping:
+                  time per W_h application on the random-c^2 square at 256^2
+                  .. 2048^2 (omega scaled with n), and a CG solve to 1e-8 on
+                  512^2 (omega = 50) with each
   --mode adjoint  receiver-misfit gradient on 1024^2 (omega = 60, 8 sources,
                   128 receivers on a ring, data from a slower inclusion):
                   forward solve, adjoint solve and checkpointed reverse sweep
@@ -66,7 +71,10 @@ def parse():
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint", "implicit"], default="solve")
+    ap.add_argument("--nits", type=int, default=10, help="--mode implicit: implicit steps per period")
+    ap.add_argument("--sizes", default="256,512,1024,2048", help="--mode implicit: grid sizes compared")
+    ap.add_argument("--skip-solve", action="store_true", help="--mode implicit: only the per-application times")
     ap.add_argument("--count", type=int, default=64, help="problems in --mode batch")
     ap.add_argument("--no-sequential", dest="sequential", action="store_false", default=True,
                     help="--mode batch: skip the one-at-a-time comparison")
@@ -84,6 +92,74 @@ def parse():
     if cube and args.mode != "kernel":
         ap.error("--workload cube is measured with --mode kernel")
     return args
+
+
+def run_implicit(args, dev):
+    """Implicit against explicit stepping on the random-c^2 square (4th order,
+    FP64): per-application times at fixed points per wavelength and one solve
+    to the residual target."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    rows = []
+    for n in [int(x) for x in args.sizes.split(",")]:
+        omega = 200.0 * n / 2048
+        w = wl.smooth_random_speed_sources(n=n, order=4, omega=omega)
+        s = Solver(2, (n, n), order=4, restart=2)
+        s.set_c2(w["c2"])
+        s.set_source(w["f"])
+        tp_e = s.set_frequency(omega)
+        g = torch.Generator(device=dev)
+        g.manual_seed(7)
+        v = torch.randn(s.shape, dtype=torch.float64, device=dev, generator=g)
+        out = s.new()
+
+        def per_apply(reps):
+            s.apply_A(v, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.apply_A(v, out=out)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        te = per_apply(10)
+        s.set_implicit(args.nits, 1e-10)
+        s.set_frequency(omega)
+        st0 = s.implicit_stats()
+        ti = per_apply(3)
+        st1 = s.implicit_stats()
+        inner = (st1["inner_iters"] - st0["inner_iters"]) / max(1, st1["steps"] - st0["steps"])
+        rows.append({"n": n, "omega": omega, "explicit_nt": tp_e["nt"], "explicit_ms_per_apply": round(te * 1e3, 3),
+                     "implicit_nits": args.nits, "implicit_ms_per_apply": round(ti * 1e3, 3),
+                     "inner_cg_iters_per_step": round(inner, 2), "mg_levels": st1["levels"],
+                     "implicit_ns_per_node_step": round(ti * 1e9 / ((n - 1) ** 2 * args.nits), 3)})
+        log(f"implicit vs explicit: {rows[-1]}")
+        del s
+        torch.cuda.empty_cache()
+    n, omega = 512, 50.0
+    w = wl.smooth_random_speed_sources(n=n, order=4, omega=omega)
+    solves = {}
+    for mode in (() if args.skip_solve else ("explicit", "implicit")):
+        s = Solver(2, (n, n), order=4, restart=2)
+        s.set_c2(w["c2"])
+        s.set_source(w["f"])
+        if mode == "implicit":
+            s.set_implicit(args.nits, 1e-10)
+        s.set_frequency(omega)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(method="cg", rtol=args.rtol, maxit=20000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solves[mode] = {"seconds": round(dt, 3), "iters": info["iters"], "applies": info["applies"],
+                        "converged": info["converged"], "rel_res": info["rel_res"],
+                        "helmholtz_rel_res": s.helmholtz_residual(x)}
+        log(f"solve 512^2 {mode}: {solves[mode]}")
+        del s
+    print(json.dumps({"mode": "implicit", "workload": "square, order 4, random c^2 in [0.5,2], omega = 200 n/2048, "
+                      "4 Gaussian sources, FP64; implicit steps solved by CG with a multigrid V-cycle to 1e-10",
+                      "per_apply": rows, "solve_512": solves}), flush=True)
 
 
 def run_cube_kernel(args, dev):
@@ -441,6 +517,9 @@ def main():
         return
     if args.mode == "adjoint":
         run_adjoint(args, dev)
+        return
+    if args.mode == "implicit":
+        run_implicit(args, dev)
         return
     if args.workload == "cube":
         run_cube_kernel(args, dev)

@@ -73,6 +73,9 @@ struct wh_ctx {
   std::vector<MgLevel> mg;
   double dconst = 1.0;  // 1/c^2 when c^2 is constant (d == nullptr)
   bool mg_ready = false;
+  hipStream_t mg_cap = nullptr;  // capture stream of the V-cycle graph
+  hipGraph_t mg_graph = nullptr;
+  hipGraphExec_t mg_exec = nullptr;
   double *imp_r = nullptr, *imp_z = nullptr, *imp_p = nullptr, *imp_q = nullptr;
   double *imp_part = nullptr, *imp_scal = nullptr;
   int64_t imp_steps = 0, imp_iters = 0;
@@ -414,6 +417,17 @@ wh::MgGeom mg_geom(int nx, int ny, int order, double theta) {
   return g;
 }
 
+wh_status mg_vcycle(wh_ctx *c, size_t l, hipStream_t s);
+
+wh_status mg_drop_graph(wh_ctx *c) {
+  if (c->mg_exec || c->mg_graph) WH_HIP(c, hipStreamSynchronize(c->stream));  // no replay in flight
+  if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
+  if (c->mg_graph) (void)hipGraphDestroy(c->mg_graph);
+  c->mg_exec = nullptr;
+  c->mg_graph = nullptr;
+  return WH_OK;
+}
+
 wh_status mg_setup(wh_ctx *c) {
   if (!c->imp) return fail(c, WH_ESTATE, "implicit stepping needs its workspace (wh_bind_implicit_workspace)");
   const ImpLayout L = imp_layout(c);
@@ -449,35 +463,60 @@ wh_status mg_setup(wh_ctx *c) {
   }
   c->imp_part = at(k);
   c->imp_scal = at(k + 1);
+  // coarsen only while the level's operator is far from its diagonal: once
+  // theta n^2 <= 1/2 damped Jacobi alone solves it well
+  size_t used = 1;
+  while (used < c->mg.size()) {
+    const wh::MgGeom &gl = c->mg[used - 1].g;
+    const double nmax = (double)std::max(gl.nx, gl.ny);
+    if (theta * nmax * nmax <= 0.5) break;
+    ++used;
+  }
+  c->mg.resize(used);
   if (cvar) {
     WH_HIP(c, wh::launch_mg_inverse(c->mg[0].g, static_cast<const double *>(c->c2), c->mg[0].d, c->stream));
     for (size_t l = 1; l < c->mg.size(); ++l)
       WH_HIP(c, wh::launch_mg_inject(c->mg[l - 1].g, c->mg[l - 1].d, c->mg[l].g, c->mg[l].d, c->stream));
   }
+  // the V-cycle is a fixed sequence of launches on fixed buffers: capture it
+  // once (on the context's own capture stream) and replay it per iteration
+  WH_TRY(mg_drop_graph(c));
+  if (!c->mg_cap) WH_HIP(c, hipStreamCreateWithFlags(&c->mg_cap, hipStreamNonBlocking));
+  WH_HIP(c, hipStreamBeginCapture(c->mg_cap, hipStreamCaptureModeThreadLocal));
+  const wh_status st = mg_vcycle(c, 0, c->mg_cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->mg_cap, &graph);
+  if (st != WH_OK || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != WH_OK) return st;
+    return fail(c, WH_EDEVICE, "V-cycle graph capture failed: %s", hipGetErrorString(ec));
+  }
+  c->mg_graph = graph;
+  WH_HIP(c, hipGraphInstantiate(&c->mg_exec, graph, nullptr, nullptr, 0));
   c->mg_ready = true;
   return WH_OK;
 }
 
 // x_l = V-cycle approximation of S_l^{-1} b_l (x_l starts from 0).
-wh_status mg_vcycle(wh_ctx *c, size_t l) {
+wh_status mg_vcycle(wh_ctx *c, size_t l, hipStream_t s) {
   wh_ctx::MgLevel &L = c->mg[l];
   const double w = L.g.order == 4 ? 0.75 : 0.8;
   const int sweeps = l + 1 == c->mg.size() ? kMgCoarseSweeps : kMgPreSweeps;
   // damped Jacobi from x = 0, ping-ponging between t and x (even count: ends in x)
-  WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, nullptr, L.b, L.t, w, c->stream));
+  WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, nullptr, L.b, L.t, w, s));
   for (int sw = 1; sw < sweeps; ++sw) {
     const bool to_x = (sw & 1) != 0;
-    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_x ? L.t : L.x, L.b, to_x ? L.x : L.t, w, c->stream));
+    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_x ? L.t : L.x, L.b, to_x ? L.x : L.t, w, s));
   }
   if (l + 1 == c->mg.size()) return WH_OK;
   wh_ctx::MgLevel &C = c->mg[l + 1];
-  WH_HIP(c, wh::launch_mg_residual(L.g, L.d, c->dconst, L.x, L.b, L.t, c->stream));
-  WH_HIP(c, wh::launch_mg_restrict(L.g, L.t, C.g, C.b, c->stream));
-  WH_TRY(mg_vcycle(c, l + 1));
-  WH_HIP(c, wh::launch_mg_prolong(C.g, C.x, L.g, L.x, c->stream));
+  WH_HIP(c, wh::launch_mg_residual(L.g, L.d, c->dconst, L.x, L.b, L.t, s));
+  WH_HIP(c, wh::launch_mg_restrict(L.g, L.t, C.g, C.b, s));
+  WH_TRY(mg_vcycle(c, l + 1, s));
+  WH_HIP(c, wh::launch_mg_prolong(C.g, C.x, L.g, L.x, s));
   for (int sw = 0; sw < kMgPreSweeps; ++sw) {
     const bool to_t = (sw & 1) == 0;
-    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_t ? L.x : L.t, L.b, to_t ? L.t : L.x, w, c->stream));
+    WH_HIP(c, wh::launch_mg_smooth(L.g, L.d, c->dconst, to_t ? L.x : L.t, L.b, to_t ? L.t : L.x, w, s));
   }
   return WH_OK;
 }
@@ -517,7 +556,7 @@ wh_status pcg_solve(wh_ctx *c, double *x) {
   WH_TRY(imp_fetch(c, 2, &rr));
   int it = 0;
   if (rr > tol2) {
-    WH_TRY(mg_vcycle(c, 0));  // z = B_mg r
+    WH_HIP(c, hipGraphLaunch(c->mg_exec, c->stream));  // z = V-cycle(r)
     WH_TRY(imp_dot(c, r, z, 0));
     WH_HIP(c, wh::launch_pcg_xpay(N, z, p, nullptr, nullptr, c->stream));
     while (true) {
@@ -532,7 +571,7 @@ wh_status pcg_solve(wh_ctx *c, double *x) {
       if (it >= kImpMaxInner)
         return fail(c, WH_ENOTCONV, "implicit step: inner CG did not reach %g in %d iterations (at %g)",
                     c->imp_rtol, it, std::sqrt(rr / bb));
-      WH_TRY(mg_vcycle(c, 0));
+      WH_HIP(c, hipGraphLaunch(c->mg_exec, c->stream));
       WH_TRY(imp_dot(c, r, z, 3));
       WH_HIP(c, wh::launch_pcg_xpay(N, z, p, c->imp_scal + 3, c->imp_scal + 0, c->stream));
       WH_HIP(c, hipMemcpyAsync(c->imp_scal + 0, c->imp_scal + 3, 8, hipMemcpyDeviceToDevice, c->stream));
@@ -849,6 +888,12 @@ void wh_destroy(wh_ctx *c) {
     (void)hipEventDestroy(t.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->mg_exec || c->mg_graph) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
+    if (c->mg_graph) (void)hipGraphDestroy(c->mg_graph);
+  }
+  if (c->mg_cap) (void)hipStreamDestroy(c->mg_cap);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
@@ -1949,7 +1994,7 @@ wh_status wh_implicit_stats(const wh_ctx *c, int64_t *steps, int64_t *inner_iter
   if (steps) *steps = c->imp_steps;
   if (inner_iters) *inner_iters = c->imp_iters;
   if (max_inner) *max_inner = c->imp_max;
-  if (levels) *levels = c->grid_set ? (int32_t)mg_shapes(c).size() : 0;
+  if (levels) *levels = c->mg_ready ? (int32_t)c->mg.size() : 0;
   return WH_OK;
 }
 

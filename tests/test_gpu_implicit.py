@@ -81,8 +81,10 @@ def test_implicit_apply_matches_oracle(torch, n, order, nits, periods):
     assert _rel(fin.cpu().numpy(), want_fin) <= TOL
     stats = s.implicit_stats()
     assert stats["steps"] == 3 * nits * periods and stats["inner_iters"] >= stats["steps"]
+    # levels: halve while both axes are even, and only while theta n^2 > 1/2
+    theta = 0.5 * tp["dt"] ** 2
     levels, (nx, ny) = 1, n
-    while nx % 2 == 0 and ny % 2 == 0 and nx >= 4 and ny >= 4:
+    while nx % 2 == 0 and ny % 2 == 0 and nx >= 4 and ny >= 4 and theta * max(nx, ny) ** 2 > 0.5:
         nx, ny, levels = nx // 2, ny // 2, levels + 1
     assert stats["levels"] == levels
 
