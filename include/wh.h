@@ -267,7 +267,7 @@ WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *o
 /* Time-stepping kernel families.
  *   WH_KERNEL_AUTO       library choice (2-D: blocked, 6 steps per pass for
  *                        p = 4, 8 for p = 2; 3-D: blocked, 4 steps per pass
- *                        for p = 2, 2 for p = 4)
+ *                        for p = 2, 3 for p = 4 FP32, 2 for p = 4 FP64)
  *   WH_KERNEL_NODE       one node per thread, one step per launch (2-D, 3-D)
  *   WH_KERNEL_BLOCKED_2D kblock leapfrog steps per launch (p = 4: 2..6; p = 2:
  *                        2, 3, 4, 6, 8); tile = rows of the region a
@@ -276,10 +276,10 @@ WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *o
  *                        halo kblock*p/2 included
  *   WH_KERNEL_ZCOL_3D    one step per launch; tile = consecutive z nodes per
  *                        thread (4, 8, 16), z-neighbours kept in registers
- *   WH_KERNEL_BLOCKED_3D kblock (1..4; p = 4 FP32 and FP64 32-row tiles:
- *                        1..2) leapfrog steps per launch, pipelined along z
- *                        over (x, y) tiles of 64 columns; tile = rows of the
- *                        tile (16 or 32; 0 = default), halo kblock*p/2
+ *   WH_KERNEL_BLOCKED_3D kblock (1..4; FP64 p = 4: 1..2) leapfrog steps per
+ *                        launch, pipelined along z over (x, y) tiles of 64
+ *                        columns; tile = rows of the tile (16 or 32, more
+ *                        than 2*kblock*p/2; 0 = default), halo kblock*p/2
  *                        included
  * Every family evaluates the same expression per node and step; results
  * agree with each other to rounding. */

@@ -54,19 +54,21 @@ hipError_t launch_batch_block_steps(bool fp32, int order, int K, int rows, bool 
 // ---- 3-D: z-pipelined blocked kernel ----
 int block3d_rows_per_lane(bool fp32) { return fp32 ? Rows3d<float>::RS : Rows3d<double>::RS; }
 
-// LDS of the double-buffered y-halo of all K levels; kept within 64 KB
+// LDS of the double-buffered y-halo of all K levels (at most one CU's 160 KB)
 static int block3d_lds(bool fp32, int order, int K, int nw) {
   return 2 * K * nw * 2 * (order / 2) * 64 * (fp32 ? 4 : 8);
 }
 
 bool block3d_config_supported(bool fp32, int order, int K, int rows) {
   if (!(order == 2 || order == 4) || K < 1 || K > kMaxBlockSteps3d) return false;
+  // FP64 p = 4 rings of 3 or more levels do not fit the registers (they spill)
+  if (!fp32 && order == 4 && K > 2) return false;
   const int rs = block3d_rows_per_lane(fp32);
   if (rows % rs != 0) return false;
   const int nw = rows / rs;
   if (fp32 ? (nw != 8 && nw != 16) : (nw != 4 && nw != 8)) return false;
   const int H = K * (order / 2);
-  return rows - 2 * H > 0 && 64 - 2 * H > 0 && block3d_lds(fp32, order, K, nw) <= 65536;
+  return rows - 2 * H > 0 && 64 - 2 * H > 0 && block3d_lds(fp32, order, K, nw) <= kBlock3dMaxLds;
 }
 
 // the larger group where it fits (FP32 16 waves, FP64 8)

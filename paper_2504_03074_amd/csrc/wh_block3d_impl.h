@@ -59,6 +59,9 @@ struct Pipe3d {
   static constexpr int LC = H + 1;
 };
 
+// LDS of one CU on gfx950 (160 KB): the limit of the double-buffered halo
+constexpr int kBlock3dMaxLds = 160 * 1024;
+
 template <typename T, int P, int K, int NW>
 constexpr int block3d_lds_bytes() {
   return 2 * K * NW * 2 * (P / 2) * 64 * (int)sizeof(T);
@@ -351,7 +354,7 @@ hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in
                           double *acc, const void *c2, const void *f, const BlockCoef &coef, int mode,
                           const double *v, double *out, hipStream_t s) {
   constexpr int RS = Rows3d<T>::RS;
-  if constexpr (NW * RS - 2 * K * (P / 2) > 0 && block3d_lds_bytes<T, P, K, NW>() <= 65536) {
+  if constexpr (NW * RS - 2 * K * (P / 2) > 0 && block3d_lds_bytes<T, P, K, NW>() <= kBlock3dMaxLds) {
     constexpr int H = K * (P / 2);
     constexpr int OX = 64 - 2 * H;
     constexpr int OY = NW * RS - 2 * H;
