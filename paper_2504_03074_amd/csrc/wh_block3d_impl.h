@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "wh_block_impl.h"
 #include "wh_internal.h"
@@ -67,8 +68,20 @@ constexpr int block3d_lds_bytes() {
   return 2 * K * NW * 2 * (P / 2) * 64 * (int)sizeof(T);
 }
 
+// Planes loaded ahead of the one entering the pipeline (1 or 2).  One is the
+// fastest measured: two planes ahead cost FP32 enough registers to lose more
+// to occupancy (p = 2, K = 4: 362 against 394 GPts/s) than the extra loads in
+// flight gain; FP64 rings already fill the registers.
+#ifndef WH_BLOCK3D_PREFETCH_F32
+#define WH_BLOCK3D_PREFETCH_F32 1
+#endif
+template <typename T>
+struct Prefetch3d {
+  static constexpr int PD = sizeof(T) == 8 ? 1 : WH_BLOCK3D_PREFETCH_F32;
+};
+
 // K leapfrog steps of the owned planes [z0, z1) of tile (tx, ty).
-template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR, bool INNER>
+template <typename T, int P, int K, int RS, int NW, int PD, bool FORCE, bool CVAR, bool INNER>
 __device__ __forceinline__ void advance_column_impl(
     const StepGeom &g, int tx, int ty, int z0, int z1, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
     T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
@@ -131,25 +144,32 @@ __device__ __forceinline__ void advance_column_impl(
   const int64_t sz = g.sz;
   const int nit = (z1 - z0) + 2 * H;
 
-  // Loads run one plane ahead: the next plane of W^{n-1}, W^n and c^2, and
+  // Loads run PD planes ahead: the coming planes of W^{n-1}, W^n and c^2, and
   // the accumulator of the output plane, are in flight during the LDS
-  // exchange and the K steps of the current plane.
-  T NA[RS], NB[RS], NC[CVAR ? RS : 1];
-  auto load_plane = [&](int zl) -> T {
+  // exchange and the K steps of the current plane.  Iterations alternate
+  // over PD staging slots (unrolled, so the slots stay in registers).
+  T NA[PD][RS], NB[PD][RS], NC[PD][CVAR ? RS : 1];
+  T nsg[PD];
+  auto load_plane = [&](auto slot_c, int zl) -> T {
+    constexpr int slot = decltype(slot_c)::value;
     float szs = 1.0f;
     const int iz = reflect(zl, g.nz, szs);  // odd reflection across the z walls
     const int64_t pb = (int64_t)iz * sz;
 #pragma unroll
     for (int q = 0; q < RS; ++q) {
-      NA[q] = ld_at(in_cur + pb, off[q]);
-      NB[q] = ld_at(in_prev + pb, off[q]);
-      if constexpr (CVAR) NC[q] = ld_at(c2g + pb, off[q]);
+      NA[slot][q] = ld_at(in_cur + pb, off[q]);
+      NB[slot][q] = ld_at(in_prev + pb, off[q]);
+      if constexpr (CVAR) NC[slot][q] = ld_at(c2g + pb, off[q]);
     }
     return static_cast<T>(szs);
   };
-  T nsg = load_plane(z0 - H);
+  nsg[0] = load_plane(std::integral_constant<int, 0>{}, z0 - H);
+  if constexpr (PD == 2) {
+    if (nit > 1) nsg[PD - 1] = load_plane(std::integral_constant<int, PD - 1>{}, z0 - H + 1);
+  }
 
-  for (int it = 0; it < nit; ++it) {
+  auto iterate = [&](int it, auto slot_c) {
+    constexpr int slot = decltype(slot_c)::value;
     const int zp = z0 - H + it;  // plane entering the pipeline in this iteration
     // age every ring by one plane
 #pragma unroll
@@ -169,9 +189,9 @@ __device__ __forceinline__ void advance_column_impl(
     // take the staged plane zp (reflection signs: uniform in z, per row in x, y)
 #pragma unroll
     for (int q = 0; q < RS; ++q) {
-      WV[q][0] = NA[q];
-      WP[q][0] = NB[q];
-      if constexpr (CVAR) CB[q][0] = NC[q] * kx;
+      WV[q][0] = NA[slot][q];
+      WP[q][0] = NB[slot][q];
+      if constexpr (CVAR) CB[q][0] = NC[slot][q] * kx;
     }
     if (!INNER) {
 #pragma unroll
@@ -180,14 +200,14 @@ __device__ __forceinline__ void advance_column_impl(
         WP[q][0] *= sgn[q];
       }
     }
-    if (nsg < T(0)) {
+    if (nsg[slot] < T(0)) {
 #pragma unroll
       for (int q = 0; q < RS; ++q) {
         WV[q][0] = -WV[q][0];
         WP[q][0] = -WP[q][0];
       }
     }
-    if (it + 1 < nit) nsg = load_plane(zp + 1);
+    if (it + PD < nit) nsg[slot] = load_plane(slot_c, zp + PD);
     // accumulator of the plane this iteration completes
     const int zo = zp - H;
     const bool out_plane = zo >= z0 && zo < z1;
@@ -288,6 +308,12 @@ __device__ __forceinline__ void advance_column_impl(
         else st_at(out + ob, e, ld_at(v + ob, e) - a);
       }
     }
+  };
+  for (int it = 0; it < nit; it += PD) {
+    iterate(it, std::integral_constant<int, 0>{});
+    if constexpr (PD == 2) {
+      if (it + 1 < nit) iterate(it + 1, std::integral_constant<int, PD - 1>{});
+    }
   }
 }
 
@@ -311,10 +337,10 @@ __global__ __launch_bounds__(64 * NW) void block3d_steps_kernel(
   const int x0 = tx * OX - H, y0 = ty * OY - H;
   const bool inner = x0 >= 1 && x0 + 63 <= g.nx - 1 && y0 >= 1 && y0 + NW * RS - 1 <= g.ny - 1;
   if (inner)
-    advance_column_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
+    advance_column_impl<T, P, K, RS, NW, Prefetch3d<T>::PD, FORCE, CVAR, true>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
                                                             acc, c2g, fg, coef, mode, v, out, halo);
   else
-    advance_column_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
+    advance_column_impl<T, P, K, RS, NW, Prefetch3d<T>::PD, FORCE, CVAR, false>(g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur,
                                                              acc, c2g, fg, coef, mode, v, out, halo);
 }
 
