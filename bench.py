@@ -28,6 +28,9 @@ Other modes (used to produce the committed rocprofv3 summaries):
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
                   by the batched CG, against solving them one at a time
+  --mode mixed    the default workload solved to the residual target in FP64
+                  and by residual correction (FP64 residuals, FP32-state CG
+                  corrections to 1e-3), with the FP32 and FP64 kernel rates
   --mode implicit implicit stepping (N_ITS steps per period, multigrid-
                   preconditioned CG per step) against explicit stepping:
                   time per W_h application on the random-c^2 square at 256^2
@@ -71,7 +74,8 @@ def parse():
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint", "implicit"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint", "implicit", "mixed"],
+                    default="solve")
     ap.add_argument("--nits", type=int, default=10, help="--mode implicit: implicit steps per period")
     ap.add_argument("--sizes", default="256,512,1024,2048", help="--mode implicit: grid sizes compared")
     ap.add_argument("--skip-solve", action="store_true", help="--mode implicit: only the per-application times")
@@ -92,6 +96,55 @@ def parse():
     if cube and args.mode != "kernel":
         ap.error("--workload cube is measured with --mode kernel")
     return args
+
+
+def run_mixed(args, dev):
+    """FP64 CG against mixed-precision residual correction on the default
+    workload, both to the residual target."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    w = wl.smooth_random_speed_sources(n=args.n, order=4)
+    solvers = {}
+    for prec in ("fp64", "fp32"):
+        s = Solver(2, (args.n, args.n), order=4, precision=prec, restart=2)
+        s.set_c2(w["c2"])
+        s.set_source(w["f"])
+        s.set_frequency(w["omega"])
+        solvers[prec] = s
+    rates = {}
+    for prec, s in solvers.items():
+        v = torch.zeros(s.shape, dtype=torch.float64, device=dev)
+        out = s.new()
+        s.apply_A(v, out=out)
+        s.profile_enable(True)
+        for _ in range(10):
+            s.apply_A(v, out=out)
+        pr = s.profile_read()
+        s.profile_enable(False)
+        rates[prec] = round(pr["point_steps"] / pr["ms"] * 1e-6, 1)
+    hi, lo = solvers["fp64"], solvers["fp32"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x64, i64 = hi.solve(method="cg", rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    log(f"FP64 CG: {i64['iters']} iterations, {t64:.2f}s")
+    t0 = time.perf_counter()
+    xm, im = hi.solve_mixed(lo, rtol=args.rtol, maxit=50, inner_method="cg", inner_rtol=1e-3, inner_maxit=5000)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    log(f"mixed: {im['iters']} corrections, {im['applies']} applies, {tm:.2f}s")
+    diff = float(torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64))
+    print(json.dumps({"mode": "mixed", "workload": f"square {args.n}^2, order 4, random c^2 in [0.5,2], omega=200",
+                      "kernel_GPts_per_s": rates,
+                      "fp64_cg": {"seconds": round(t64, 3), "iters": i64["iters"], "applies": i64["applies"],
+                                  "rel_res": i64["rel_res"], "converged": i64["converged"],
+                                  "helmholtz_rel_res": hi.helmholtz_residual(x64)},
+                      "mixed": {"seconds": round(tm, 3), "corrections": im["iters"], "applies": im["applies"],
+                                "rel_res": im["rel_res"], "converged": im["converged"],
+                                "helmholtz_rel_res": hi.helmholtz_residual(xm), "rel_diff_to_fp64": diff}}),
+          flush=True)
 
 
 def run_implicit(args, dev):
@@ -520,6 +573,9 @@ def main():
         return
     if args.mode == "implicit":
         run_implicit(args, dev)
+        return
+    if args.mode == "mixed":
+        run_mixed(args, dev)
         return
     if args.workload == "cube":
         run_cube_kernel(args, dev)
