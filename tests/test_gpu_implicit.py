@@ -185,3 +185,32 @@ def test_implicit_errors_and_switching(torch):
     tpe = oc.time_params(grid, 1.0, 9.0)
     got = s.apply(_dev(torch, v), with_forcing=True).cpu().numpy()
     assert _rel(got, oc.apply(grid, 1.0, f, v, tpe)) <= TOL
+
+
+def test_implicit_with_deflation(torch):
+    """Alg. 3 on top of implicit stepping (constant c^2): the modes chosen are
+    the slowest under the implicit mode map, and every inflated iterate is the
+    DST-I closed form (1 - beta_i^k) U on kept modes, U on deflated ones."""
+    _say("[implicit deflation]")
+    n = (40, 36)
+    grid = oc.Grid(2, n, 2)
+    c2, omega, nits = 1.1, 12.0, 8
+    f = wl.random_field(grid.shape, seed=841)
+    s = _solver(n, 2, c2, f, omega, nits)
+    tp = oi.time_params_implicit(omega, nits)
+    modes, mu = s.set_deflation(count=10)
+    inner = (slice(1, -1),) * 2
+    lam2 = cf.mode_eigenvalues(grid, c2)
+    beta = cf.beta_d_tp(oi.lambda_tilde_implicit(np.sqrt(lam2), tp["dt"]), tp)
+    keep = np.ones(beta.shape, dtype=bool)
+    for m in modes:
+        keep[m[1] - 1, m[0] - 1] = False
+    assert np.abs(beta[~keep]).min() >= np.abs(beta[keep]).max()
+    assert mu == pytest.approx(float(np.abs(beta[keep]).max()), rel=1e-10)
+    U = cf._dst(f[inner]) / (omega ** 2 - lam2)
+    for k in (1, 5):
+        v, info = s.solve(method="fpi", rtol=0.0, maxit=k)
+        V = np.where(keep, (1.0 - beta ** k) * U, U)
+        want = np.zeros(grid.shape)
+        want[inner] = cf._idst(V)
+        assert _rel(v.cpu().numpy(), want) <= TOL, k
