@@ -190,6 +190,39 @@ def run_implicit(args, dev):
         log(f"implicit vs explicit: {rows[-1]}")
         del s
         torch.cuda.empty_cache()
+    # fixed omega: the explicit N_t grows like n, the implicit one does not
+    fixed = []
+    for n in ([] if args.skip_solve else [512, 1024, 2048, 4096]):
+        omega = 50.0
+        w = wl.smooth_random_speed_sources(n=n, order=4, omega=omega)
+        s = Solver(2, (n, n), order=4, restart=2)
+        s.set_c2(w["c2"])
+        s.set_source(w["f"])
+        tp_e = s.set_frequency(omega)
+        del w
+        g = torch.Generator(device=dev)
+        g.manual_seed(8)
+        v = torch.randn(s.shape, dtype=torch.float64, device=dev, generator=g)  # a zero input skips the solves
+        out = s.new()
+
+        def per_apply_fixed(reps):
+            s.apply_A(v, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.apply_A(v, out=out)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        te = per_apply_fixed(3)
+        s.set_implicit(args.nits, 1e-10)
+        s.set_frequency(omega)
+        ti = per_apply_fixed(2)
+        fixed.append({"n": n, "omega": omega, "explicit_nt": tp_e["nt"], "explicit_ms_per_apply": round(te * 1e3, 3),
+                      "implicit_nits": args.nits, "implicit_ms_per_apply": round(ti * 1e3, 3)})
+        log(f"fixed omega: {fixed[-1]}")
+        del s
+        torch.cuda.empty_cache()
     n, omega = 512, 50.0
     w = wl.smooth_random_speed_sources(n=n, order=4, omega=omega)
     solves = {}
@@ -212,7 +245,7 @@ def run_implicit(args, dev):
         del s
     print(json.dumps({"mode": "implicit", "workload": "square, order 4, random c^2 in [0.5,2], omega = 200 n/2048, "
                       "4 Gaussian sources, FP64; implicit steps solved by CG with a multigrid V-cycle to 1e-10",
-                      "per_apply": rows, "solve_512": solves}), flush=True)
+                      "per_apply": rows, "per_apply_fixed_omega_50": fixed, "solve_512": solves}), flush=True)
 
 
 def run_cube_kernel(args, dev):
