@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--nits", type=int, default=10, help="--mode implicit: implicit steps per period")
     ap.add_argument("--sizes", default="256,512,1024,2048", help="--mode implicit: grid sizes compared")
     ap.add_argument("--skip-solve", action="store_true", help="--mode implicit: only the per-application times")
+    ap.add_argument("--fixed-sizes", default="512,1024,2048,4096",
+                    help="--mode implicit: grid sizes of the fixed-omega (omega = 50) series")
     ap.add_argument("--count", type=int, default=64, help="problems in --mode batch")
     ap.add_argument("--no-sequential", dest="sequential", action="store_false", default=True,
                     help="--mode batch: skip the one-at-a-time comparison")
@@ -192,7 +194,7 @@ def run_implicit(args, dev):
         torch.cuda.empty_cache()
     # fixed omega: the explicit N_t grows like n, the implicit one does not
     fixed = []
-    for n in ([] if args.skip_solve else [512, 1024, 2048, 4096]):
+    for n in ([] if args.skip_solve else [int(x) for x in args.fixed_sizes.split(",") if x]):
         omega = 50.0
         w = wl.smooth_random_speed_sources(n=n, order=4, omega=omega)
         s = Solver(2, (n, n), order=4, restart=2)
