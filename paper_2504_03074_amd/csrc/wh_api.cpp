@@ -954,6 +954,8 @@ wh_status wh_set_grid(wh_ctx *c, int32_t dim, const int64_t n[3], int32_t order,
   c->imp = nullptr;
   c->imp_bytes = 0;
   c->mg_ready = false;
+  c->imp_steps = c->imp_iters = 0;
+  c->imp_max = 0;
   c->err.clear();
   return WH_OK;
 }
