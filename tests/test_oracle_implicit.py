@@ -148,3 +148,19 @@ def test_planted_implicit_mistake_is_caught(tmp_path, desc, old, new):
     except Exception:
         return
     assert bad_modes or bad_fixed, desc
+
+
+@pytest.mark.parametrize("nits", [5, 10, 20])
+def test_mode_map_limit(nits):
+    """The implicit mode map saturates: lambda~_i tends to omega_i N_t / 4 as
+    lambda grows (stated with the figure of the adjusted lambda, Sec. 4.2.2),
+    and it is increasing, with lambda~_i ~ lambda for lambda dt -> 0."""
+    tp = oi.time_params_implicit(3.0, nits)
+    dt, wi = tp["dt"], tp["omega_e"]
+    big = oi.lambda_tilde_implicit(1e9 / dt, dt)
+    assert big == pytest.approx(wi * nits / 4.0, rel=1e-9)
+    lam = np.linspace(1e-3, 50.0, 200) / dt
+    lt = oi.lambda_tilde_implicit(lam, dt)
+    assert np.all(np.diff(lt) > 0)
+    small = 1e-4 / dt
+    assert oi.lambda_tilde_implicit(small, dt) == pytest.approx(small, rel=1e-8)
