@@ -569,7 +569,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is designed "
+        print(json.dumps({"error": "the WaveHoltz library runs on one GPU only; multi-GPU sharding is designed "
                                    "(slab decomposition with halo exchange) but not built",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
