@@ -340,6 +340,29 @@ def cpu_baseline(w, order, nt_sample):
     return pts / sec / 1e9, oc.max_threads(), sec, tp["nt"]
 
 
+def cpu_single_thread(w, order, steps=12):
+    """The same oracle on one thread, over `steps` leapfrog steps of the same
+    grid (the rate per point-step does not depend on the step count)."""
+    from oracle import core as oc
+    threads = oc.max_threads()
+    oc.set_threads(1)
+    try:
+        rate, _, sec, nt = cpu_baseline(w, order, steps)
+    finally:
+        oc.set_threads(threads)
+    return rate, sec, nt
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def run_batch(args, dev):
     """Many independent solves at once: the batched CG (one launch per blocked
     pass over all problems, the iteration replayed from a HIP graph) against
@@ -742,8 +765,11 @@ def main():
     if args.cpu_baseline:
         log("CPU oracle baseline: one W_h(v, 0) application on the host")
         rate, cores, sec, nt = cpu_baseline(dict(w, n=args.n), order, None)
+        rate1, sec1, nt1 = cpu_single_thread(dict(w, n=args.n), order)
         result["cpu_baseline"] = {
             "value": round(rate, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": round(rate1, 4), "cpu_model": cpu_model(),
+            "single_thread_sample": f"{nt1} leapfrog steps of the same grid on one thread, {sec1:.1f}s",
             "sample": f"one W_h(v,0) application ({nt} leapfrog steps over {unknowns} unknowns) of the same "
                       f"workload, FP64, {sec:.1f}s; CPU time to residual extrapolated as "
                       f"{applies / args.steps} applies x {sec:.1f}s = {applies / args.steps * sec:.0f}s",

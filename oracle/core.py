@@ -68,6 +68,8 @@ def _load():
                                            ctypes.c_double, dp]
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -424,3 +426,8 @@ def cg(grid: Grid, c2, f, tp: dict, rtol: float = 1e-8, maxit: int = 1000, x0=No
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the C oracle's parallel loops (for timing)."""
+    _load().orc_set_threads(int(n))

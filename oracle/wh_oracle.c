@@ -270,3 +270,14 @@ int orc_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following parallel regions (timing only; no effect when
+ * built without OpenMP or for n < 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
