@@ -270,6 +270,26 @@ def test_3d_blocked_unsupported_tunings(torch):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_3d_keeps_results(torch, prec):
+    """3-D: the autotuner times the node, z-column and blocked 3-D kernels and
+    keeps the fastest; the chosen kernel still matches the oracle."""
+    _say(f"[autotune 3d] {prec}")
+    n = (70, 41, 33)
+    grid, c2, f, v = _problem(3, n, 2, "var", seed=431)
+    s = _solver(3, n, 2, prec)
+    s.set_c2(c2)
+    s.set_source(f)
+    s.set_frequency(9.0)
+    best = s.autotune(1)
+    assert best["kernel"] in ("node", "zcol_3d", "blocked_3d") and best["ms_per_apply"] > 0
+    t = s.tuning()
+    assert (t["kernel"], t["kblock"], t["tile"]) == (best["kernel"], best["kblock"], best["tile"])
+    tp = oc.time_params(grid, c2, 9.0)
+    got = s.apply(_to_dev(torch, v), with_forcing=True).cpu().numpy()
+    assert _err(prec, got, oc.apply(grid, c2, f, v, tp, with_forcing=True), v) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_autotune_keeps_results(torch, prec):
     _say(f"[autotune] {prec}")
     grid, c2, f, v = _problem(2, (300, 257), 2, "var", seed=411)
