@@ -528,10 +528,11 @@ wh_status imp_dot(wh_ctx *c, const double *x, const double *y, int slot) {
   return WH_OK;
 }
 
-wh_status imp_fetch(wh_ctx *c, int slot, double *out) {
-  WH_HIP(c, hipMemcpyAsync(c->pinned, c->imp_scal + slot, 8, hipMemcpyDeviceToHost, c->stream));
+// Copy count scalars from slot on to the host (one synchronisation).
+wh_status imp_fetch(wh_ctx *c, int slot, double *out, int count = 1) {
+  WH_HIP(c, hipMemcpyAsync(c->pinned, c->imp_scal + slot, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream));
   WH_HIP(c, hipStreamSynchronize(c->stream));
-  *out = c->pinned[0];
+  std::memcpy(out, c->pinned, (size_t)count * 8);
   return WH_OK;
 }
 
@@ -564,10 +565,17 @@ wh_status pcg_solve(wh_ctx *c, double *x) {
       WH_TRY(imp_dot(c, p, q, 1));
       WH_HIP(c, wh::launch_pcg_update(N, x, r, p, q, c->imp_scal + 0, c->imp_scal + 1, c->stream));
       WH_TRY(imp_dot(c, r, r, 2));
-      WH_TRY(imp_fetch(c, 2, &rr));
+      double sc[3];  // r.z, p.Sp of this iteration, then the new r.r
+      WH_TRY(imp_fetch(c, 0, sc, 3));
+      rr = sc[2];
       ++it;
       if (!std::isfinite(rr)) return fail(c, WH_ENONFINITE, "implicit step: inner CG became non-finite");
       if (rr <= tol2) break;
+      // S and the V-cycle are both symmetric positive definite in exact
+      // arithmetic; a non-positive r.z or p.Sp means one of them is not
+      if (!(sc[0] > 0.0 && sc[1] > 0.0))
+        return fail(c, WH_ENOTCONV, "implicit step: inner CG lost positive definiteness (r.z = %g, p.Sp = %g) "
+                    "after %d iterations", sc[0], sc[1], it);
       if (it >= kImpMaxInner)
         return fail(c, WH_ENOTCONV, "implicit step: inner CG did not reach %g in %d iterations (at %g)",
                     c->imp_rtol, it, std::sqrt(rr / bb));
