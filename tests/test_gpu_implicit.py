@@ -214,3 +214,39 @@ def test_implicit_with_deflation(torch):
         want = np.zeros(grid.shape)
         want[inner] = cf._idst(V)
         assert _rel(v.cpu().numpy(), want) <= TOL, k
+
+
+def test_implicit_sine_modes_square_2048(torch):
+    """The implicit rate theorem at the full 2048^2 size (p = 4, constant c^2,
+    omega = 200, N_ITS = 10), through the whole multigrid hierarchy: sine
+    modes come back scaled by beta_d(lambda~_i).  Inner tolerance 1e-12: the
+    step operator's condition number here is about 350, so a tighter
+    relative residual is near the rounding floor; the error budget of each
+    solve is then about 1e-12 relative for these low and middle modes."""
+    _say("[implicit sine 2048]")
+    n = (2048, 2048)
+    order, c2, omega, nits = 4, 1.3, 200.0, 10
+    from paper_2504_03074_amd import Solver
+    s = Solver(2, n, order=order, restart=2)
+    s.set_c2(c2)
+    s.set_source(np.zeros((n[1] + 1, n[0] + 1)))
+    s.set_implicit(nits, 1e-12)
+    s.set_frequency(omega)
+    tp = oi.time_params_implicit(omega, nits)
+    for k in [(1, 1), (5, 3), (200, 150)]:
+        phi = np.multiply.outer(np.sin(k[1] * math.pi * np.arange(n[1] + 1) / n[1]),
+                                np.sin(k[0] * math.pi * np.arange(n[0] + 1) / n[0]))
+        lam = math.sqrt(c2 * sum(float(cf.lambda_h_sq_1d(km * math.pi, 1.0 / nm, order)) for km, nm in zip(k, n)))
+        beta = float(cf.beta_d_tp(oi.lambda_tilde_implicit(lam, tp["dt"]), tp))
+        got = s.apply(_dev(torch, phi), with_forcing=False).cpu().numpy()
+        err = float(np.abs(got - beta * phi).max())
+        _say(f"  mode {k}: beta {beta:.6f} max error {err:.2e}")
+        assert err <= 1e-10 * max(1.0, abs(beta)), k
+    stats = s.implicit_stats()
+    theta = 0.5 * tp["dt"] ** 2
+    levels, m = 1, n[0]
+    while m % 2 == 0 and m >= 4 and theta * m ** 2 > 0.5:
+        m, levels = m // 2, levels + 1
+    assert stats["levels"] == levels and levels >= 4
+    # multigrid-preconditioned CG: the inner count does not grow with the grid
+    assert stats["max_inner"] <= 20, stats
