@@ -24,6 +24,11 @@ Other modes (used to produce the committed rocprofv3 summaries):
   --mode kernel   only W_h applications (A v) of the workload, no solver;
                   with --workload cube: the 512^3 cube (c = 1 with a c = 1.5
                   ball, omega = 80, point-like source, 2nd order, FP32 state)
+  --mode solve --workload cube
+                  the same cube solved to the residual target by CG in the
+                  1/c^2 inner product with FP64 state (FP32 state alone does
+                  not reach 1e-8); prints progress every 200 iterations and
+                  one JSON line with the time to residual (about ten minutes)
   --mode copy     a plain device copy of known size (HBM counter calibration)
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
@@ -61,9 +66,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=1, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before timing")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
-                    help="state precision (default: fp64 for the square, fp32 for the cube)")
+                    help="state precision (default: fp64, fp32 for --mode kernel on the cube)")
     ap.add_argument("--workload", choices=["square", "cube"], default="square",
-                    help="square: 2048^2 random c^2 (default); cube: 512^3 inclusion, --mode kernel only")
+                    help="square: 2048^2 random c^2 (default); cube: 512^3 inclusion, --mode kernel or solve")
     ap.add_argument("--order", type=int, choices=[2, 4], default=0, help="stencil order (default: 4 square, 2 cube)")
     ap.add_argument("--n", type=int, default=0, help="cells per axis (default: 2048 square, 512 cube)")
     ap.add_argument("--solver", choices=["cg", "gmres"], default="cg")
@@ -90,13 +95,13 @@ def parse():
     args = ap.parse_args()
     cube = args.workload == "cube"
     if args.precision is None:
-        args.precision = "fp32" if cube else "fp64"
+        args.precision = "fp32" if cube and args.mode == "kernel" else "fp64"
     if not args.order:
         args.order = 2 if cube else 4
     if not args.n:
         args.n = 512 if cube else 2048
-    if cube and args.mode != "kernel":
-        ap.error("--workload cube is measured with --mode kernel")
+    if cube and args.mode not in ("kernel", "solve"):
+        ap.error("--workload cube is measured with --mode kernel or --mode solve")
     return args
 
 
@@ -289,6 +294,43 @@ def run_cube_kernel(args, dev):
                       "us_per_launch": pr["ms"] / pr["launches"] * 1e3,
                       "alg_GBps": pr["bytes"] / pr["ms"] * 1e-6,
                       "GPts_per_s": pr["point_steps"] / pr["ms"] * 1e-6}), flush=True)
+
+
+def run_cube_solve(args, dev):
+    """The 512^3 cube (omega = 80) solved once from v = 0 to the residual
+    target by CG in the 1/c^2 inner product; the time to residual is taken
+    from the solve call with the inputs resident and the context set up."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    n = args.n
+    w = wl.cube_inclusion(n=n, order=args.order)
+    s = Solver(3, (n, n, n), order=args.order, precision=args.precision, restart=2)
+    s.set_tuning(args.kernel, args.kblock, args.tile)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    tp = s.set_frequency(w["omega"])
+    del w
+    tun = s.tuning()
+    log(f"cube {n}^3 p={args.order} {args.precision}: time params {tp}, tuning {tun}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def progress(k, rel):
+        if k % 200 == 0:
+            log(f"  iteration {k}: relative residual {rel:.3e} after {time.perf_counter() - t0:.1f}s")
+
+    x, info = s.solve(method="cg", rtol=args.rtol, maxit=args.maxit, callback=progress)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    unknowns = (n - 1) ** 3
+    print(json.dumps({"mode": "solve", "workload": f"cube {n}^3, order {args.order}, c = 1 with a c = 1.5 ball, "
+                      f"omega = {tp['omega']}, point-like source, CG (1/c^2 inner product)",
+                      "precision": args.precision, "kernel": tun["kernel"], "kblock": tun["kblock"],
+                      "tile": tun["tile"], "nt": tp["nt"], "rtol": args.rtol, "converged": bool(info["converged"]),
+                      "iterations": info["iters"], "applies": info["applies"], "rel_res": info["rel_res"],
+                      "helmholtz_rel_res": s.helmholtz_residual(x), "time_to_residual_s": t,
+                      "GPts_per_s": unknowns * tp["nt"] * info["applies"] / t * 1e-9}), flush=True)
 
 
 def log(msg):
@@ -636,7 +678,10 @@ def main():
         run_mixed(args, dev)
         return
     if args.workload == "cube":
-        run_cube_kernel(args, dev)
+        if args.mode == "kernel":
+            run_cube_kernel(args, dev)
+        else:
+            run_cube_solve(args, dev)
         return
 
     order = args.order

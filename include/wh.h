@@ -267,7 +267,8 @@ WH_API wh_status wh_dot(wh_ctx *ctx, const double *x, const double *y, double *o
 /* Time-stepping kernel families.
  *   WH_KERNEL_AUTO       library choice (2-D: blocked, 6 steps per pass for
  *                        p = 4, 8 for p = 2; 3-D: blocked, 4 steps per pass
- *                        for p = 2, 3 for p = 4 FP32, 2 for p = 4 FP64)
+ *                        for p = 2 FP32, 3 for p = 2 FP64 and p = 4 FP32, 2
+ *                        for p = 4 FP64)
  *   WH_KERNEL_NODE       one node per thread, one step per launch (2-D, 3-D)
  *   WH_KERNEL_BLOCKED_2D kblock leapfrog steps per launch (p = 4: 2..6; p = 2:
  *                        2, 3, 4, 6, 8); tile = rows of the region a

@@ -324,7 +324,9 @@ Tuning resolve_tuning(const wh_ctx *c) {
   if (c->kernel == WH_KERNEL_AUTO) {
     if (c->dim == 2)
       return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32, c->order)};
-    const int k3 = c->order == 2 ? 4 : (fp32 ? 3 : 2);
+    // the fastest measured per state type and order; FP64 p = 2 at K = 4 and
+    // FP64 p = 4 at K >= 3 run out of registers and spill
+    const int k3 = c->order == 2 ? (fp32 ? 4 : 3) : (fp32 ? 3 : 2);
     if (tuning_supported(c, WH_KERNEL_BLOCKED_3D, k3, 0))
       return {WH_KERNEL_BLOCKED_3D, k3, wh::block3d_default_rows(fp32, c->order, k3)};
     return {WH_KERNEL_NODE, 1, 0};
