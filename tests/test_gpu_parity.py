@@ -631,7 +631,10 @@ def test_inclusion_cube_512_sampled(torch, order, prec):
     s.set_c2(w["c2"])
     s.set_source(w["f"])
     s.set_frequency(w["omega"])
-    assert s.tuning()["kernel"] == "blocked_3d"
+    # the automatic choice: the fastest measured steps per pass whose rings
+    # fit in registers (FP64 p = 2 at 4 steps spills)
+    want_k = {(2, "fp32"): 4, (4, "fp32"): 3, (2, "fp64"): 3}[(order, prec)]
+    assert s.tuning()["kernel"] == "blocked_3d" and s.tuning()["kblock"] == want_k
     tp = oc.time_params(grid, w["c2"], w["omega"])
     assert s.time_params["nt"] == tp["nt"]
     v = wl.random_field(grid.shape, seed=333)
