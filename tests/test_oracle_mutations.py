@@ -29,6 +29,10 @@ MUTATIONS = {
     "axes_transposed": ("for (int m = g->dim - 1; m >= 0; --m) idx = idx * (g->n[m] + 1) + ix[m];",
                         "for (int m = 0; m < g->dim; ++m) idx = idx * (g->n[m] + 1) + ix[m];"),
     "leapfrog_sign": ("2.0 * Wcur[idx] - Wprev[idx]", "2.0 * Wcur[idx] + Wprev[idx]"),
+    "residual_zero": ("res[idx] = orc_is_boundary(&g, ix) ? 0.0 : res[idx] + omega * omega * u[idx] - f[idx];",
+                      "res[idx] = 0.0;"),
+    "residual_omega_sign": ("res[idx] + omega * omega * u[idx] - f[idx]", "res[idx] - omega * omega * u[idx] - f[idx]"),
+    "residual_f_dropped": ("res[idx] + omega * omega * u[idx] - f[idx]", "res[idx] + omega * omega * u[idx]"),
 }
 
 
@@ -46,8 +50,9 @@ def _build_mutant(tmp_path, name):
 
 def _pins_pass():
     """A fast subset of the pins: eigenmodes (p = 2, 4, non-square grid, Np = 2),
-    the closed-form fixed-point iterates with a source, and a variable-c^2
-    operator check against the assembled sparse matrix."""
+    the closed-form fixed-point iterates with a source, a variable-c^2
+    operator check against the assembled sparse matrix, and the Helmholtz
+    residual against the same assembled operator."""
     ok = True
     for order in (2, 4):
         grid = oc.Grid(2, (14, 11), order)
@@ -71,6 +76,13 @@ def _pins_pass():
     import scipy.sparse as sp
     want = (sp.diags(c2[inner].ravel()) @ cf.laplacian_matrix(grid)) @ u[inner].ravel()
     got = oc.laplacian(grid, c2, u)[inner].ravel()
+    ok &= bool(np.abs(got - want).max() <= 1e-9 * np.abs(want).max())
+    f = wl.random_field(grid.shape, seed=5)
+    omega = 4.5
+    L = cf.laplacian_matrix(grid)
+    want = (sp.diags(c2[inner].ravel()) @ L + omega ** 2 * sp.identity(L.shape[0])) @ u[inner].ravel() \
+        - f[inner].ravel()
+    got = oc.helmholtz_residual(grid, c2, f, u, omega)[inner].ravel()
     ok &= bool(np.abs(got - want).max() <= 1e-9 * np.abs(want).max())
     return ok
 
