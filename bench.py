@@ -1,34 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the WaveHoltz hot path on one MI355X.
 
-Workload (default): the 2048^2 unit square, 4th-order stencil, smooth random
-c^2 in [0.5, 2] (seeded sum of 16 Gaussians), omega = 200, 4 random Gaussian
-sources; (I - S_h) v = b solved to ||b - A v|| <= 1e-8 ||b|| in FP64 (or FP32
-state with --precision fp32).  One step = one whole solve from v = 0 (b, every
-application of the WaveHoltz operator, the Krylov vector work), inputs
-resident in HBM.
+Workload (default): the 512^3 unit cube, 2nd-order 7-point stencil, c = 1 with
+a random ball of c = 1.5, omega = 80, point-like Gaussian source; FP32 state
+and stencil arithmetic with the filter accumulation and the Krylov vectors in
+FP64, 4 leapfrog steps per pass over HBM.  One step = a fixed block of
+--iters (default 100) conjugate-gradient iterations in the 1/c^2 inner
+product on (I - S_h) v = b from v = 0 (b = W_h(0, f), every application of the
+WaveHoltz operator, the FP64 Krylov vector work), inputs resident in HBM.
 
-Outer solver (--solver): "cg" (default) is conjugate gradients in the
-1/c^2-weighted inner product, where A = I - S_h is self-adjoint and positive
-semi-definite; "gmres" is restarted GMRES(--restart, default 50).  On this
-workload GMRES(50) stagnates near 4e-8 and never reaches 1e-8 (hundreds of
-near-resonant modes make 1 - beta_d as small as ~1e-7), so the residual target
-is reached with CG; the time-stepping kernel is the same for both.
-
-Prints one JSON line: grid-point updates per second over the solve (value),
-time to residual, the roofline of the time-stepping kernel (algorithmic bytes
-per launch over its event-timed average duration against 8 TB/s HBM), and the
-CPU oracle's rate on a bounded sample of the same workload.
+Prints one JSON line: grid-point updates per second over the timed steps
+(value), the roofline of the time-stepping kernel (algorithmic bytes per
+launch over its event-timed average duration against 8 TB/s HBM, and against
+the copy rate of the library's own streaming kernel measured in the same
+run), the CPU oracle's rate on a bounded sample of the same grid, and, as
+extra keys, the time to residual 1e-8 of the 2048^2 FP64 configuration
+(--no-square skips it).
 
 Other modes (used to produce the committed rocprofv3 summaries):
+  --workload square
+                  the 2048^2 unit square, 4th-order stencil, smooth random
+                  c^2 in [0.5, 2], omega = 200, 4 Gaussian sources, solved to
+                  ||b - A v|| <= 1e-8 ||b|| (FP64 CG by default; --solver
+                  gmres for restarted GMRES(--restart), which stagnates near
+                  4e-8 on this workload); one step = one whole solve
   --mode kernel   only W_h applications (A v) of the workload, no solver;
                   with --workload cube: the 512^3 cube (c = 1 with a c = 1.5
                   ball, omega = 80, point-like source, 2nd order, FP32 state)
-  --mode solve --workload cube
-                  the same cube solved to the residual target by CG in the
-                  1/c^2 inner product with FP64 state (FP32 state alone does
-                  not reach 1e-8); prints progress every 200 iterations and
-                  one JSON line with the time to residual (about ten minutes)
+  --mode solve --workload cube --iters 0
+                  the same cube solved towards the residual target by CG in
+                  the 1/c^2 inner product with FP64 state, at most --maxit
+                  iterations (default 2000 here: about 2.6 minutes at 79 ms
+                  per iteration; the solve stays near 5e-5 for thousands of
+                  iterations, so the target is not reached within one run);
+                  prints progress every 200 iterations and one JSON line
+  --mode stream   the library's streaming kernel (copy, read, write of 1 GiB)
   --mode copy     a plain device copy of known size (HBM counter calibration)
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
@@ -67,19 +73,24 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before timing")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="state precision (default: fp64, fp32 for --mode kernel on the cube)")
-    ap.add_argument("--workload", choices=["square", "cube"], default="square",
-                    help="square: 2048^2 random c^2 (default); cube: 512^3 inclusion, --mode kernel or solve")
+    ap.add_argument("--workload", choices=["square", "cube"], default="cube",
+                    help="cube: 512^3 inclusion (default; --mode solve or kernel); square: 2048^2 random c^2")
     ap.add_argument("--order", type=int, choices=[2, 4], default=0, help="stencil order (default: 4 square, 2 cube)")
     ap.add_argument("--n", type=int, default=0, help="cells per axis (default: 2048 square, 512 cube)")
     ap.add_argument("--solver", choices=["cg", "gmres"], default="cg")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--maxit", type=int, default=40000)
+    ap.add_argument("--maxit", type=int, default=0,
+                    help="iteration cap of a solve to the residual target (0: 40000 square, 2000 cube)")
+    ap.add_argument("--iters", type=int, default=100,
+                    help="cube: CG iterations per timed step (0: one solve towards the residual target)")
+    ap.add_argument("--no-square", dest="square", action="store_false", default=True,
+                    help="cube: skip the 2048^2 FP64 time-to-residual solve reported beside the line")
     ap.add_argument("--kernel", default="auto", help="time-stepping kernel family (auto, node, blocked_2d)")
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "batch", "adjoint", "implicit", "mixed"],
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "stream", "batch", "adjoint", "implicit", "mixed"],
                     default="solve")
     ap.add_argument("--nits", type=int, default=10, help="--mode implicit: implicit steps per period")
     ap.add_argument("--sizes", default="256,512,1024,2048", help="--mode implicit: grid sizes compared")
@@ -93,15 +104,20 @@ def parse():
     ap.add_argument("--cpu-baseline", dest="cpu_baseline", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     args = ap.parse_args()
+    # the cube is the workload of --mode solve and --mode kernel; the other
+    # modes have workloads of their own (sizes default as for the square)
+    if args.mode not in ("solve", "kernel"):
+        args.workload = "square"
     cube = args.workload == "cube"
     if args.precision is None:
-        args.precision = "fp32" if cube and args.mode == "kernel" else "fp64"
+        block = args.mode == "solve" and args.iters > 0
+        args.precision = "fp32" if cube and (args.mode == "kernel" or block) else "fp64"
+    if not args.maxit:
+        args.maxit = 2000 if cube else 40000
     if not args.order:
         args.order = 2 if cube else 4
     if not args.n:
         args.n = 512 if cube else 2048
-    if cube and args.mode not in ("kernel", "solve"):
-        ap.error("--workload cube is measured with --mode kernel or --mode solve")
     return args
 
 
@@ -333,34 +349,241 @@ def run_cube_solve(args, dev):
                       "GPts_per_s": unknowns * tp["nt"] * info["applies"] / t * 1e-9}), flush=True)
 
 
+def unblocked_bytes(precision, cvar, forcing):
+    """Algorithmic bytes of one point-step taken one step per pass: W^n and
+    W^{n-1} read, W^{n+1} written (state precision), c^2 and f read when
+    present, the FP64 accumulator read and written."""
+    t = 8 if precision == "fp64" else 4
+    return 3 * t + (t if cvar else 0) + (t if forcing else 0) + 16
+
+
+def cpu_baseline_grid(dim, n, order, c2, omega, steps, threads=None):
+    """The FP64 CPU oracle on a bounded sample of a workload: W_h(v, 0) with
+    `steps` leapfrog steps per period on the full grid, c^2 and frequency of
+    the workload (the time-step size of the full period; only the step count
+    is cut).  Returns GPts/s, the thread count and the seconds."""
+    from oracle import core as oc
+    import workloads as wl
+    grid = oc.Grid(dim, (n,) * dim, order)
+    tp = dict(oc.time_params(grid, c2, omega), nt=int(steps), periods=1)
+    v = wl.random_field(grid.shape, seed=99)
+    prev = oc.max_threads()
+    if threads:
+        oc.set_threads(threads)
+    try:
+        used = oc.max_threads()
+        t0 = time.perf_counter()
+        oc.apply(grid, c2, None, v, tp, with_forcing=False)
+        sec = time.perf_counter() - t0
+    finally:
+        oc.set_threads(prev)
+    return grid.unknowns * tp["nt"] / sec / 1e9, used, sec
+
+
+def run_square_reference(dev, log_every=0):
+    """One FP64 CG solve of the 2048^2 configuration to the residual target
+    (after one untimed application): time to residual and rate."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    w = wl.smooth_random_speed_sources(n=2048, order=4)
+    s = Solver(2, (2048, 2048), order=4, precision="fp64", restart=2)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    tp = s.set_frequency(w["omega"])
+    s.apply_A(s.new(), out=s.new())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = s.solve(method="cg", rtol=1e-8, maxit=40000)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"workload": "square 2048^2, order 4, random c^2 in [0.5,2], omega=200, 4 Gaussian sources, FP64, "
+                       "CG (1/c^2 inner product) to 1e-8",
+           "time_to_residual_s": round(t, 3), "converged": bool(info["converged"]), "iterations": info["iters"],
+           "applies": info["applies"], "rel_res": info["rel_res"], "helmholtz_rel_res": s.helmholtz_residual(x),
+           "GPts_per_s": round(2047 ** 2 * tp["nt"] * info["applies"] / t * 1e-9, 2)}
+    del s, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_cube_block(args, dev):
+    """The default benchmark: fixed blocks of CG iterations on the 512^3
+    inclusion cube with FP32 state and FP64 filter and Krylov vectors."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    n, order = args.n, args.order
+    t_setup = time.perf_counter()
+    w = wl.cube_inclusion(n=n, order=order)
+    s = Solver(3, (n, n, n), order=order, precision=args.precision, restart=2)
+    s.set_tuning(args.kernel, args.kblock, args.tile)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    tp = s.set_frequency(w["omega"])
+    tun = s.tuning()
+    log(f"cube {n}^3 p={order} {args.precision}: set up in {time.perf_counter() - t_setup:.1f}s, "
+        f"time params {tp}, tuning {tun}")
+    unknowns = (n - 1) ** 3
+    pts_per_apply = unknowns * tp["nt"] * tp["periods"]
+
+    def one_step():
+        return s.solve(method="cg", rtol=0.0, maxit=args.iters)
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        one_step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup}: {time.perf_counter() - t0:.2f}s")
+    s.profile_enable(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        x, info = one_step()
+        infos.append(info)
+        log(f"step {i + 1}/{args.steps}: {info['iters']} CG iterations, {info['applies']} applies, "
+            f"rel_res {info['rel_res']:.3e}, {info['seconds']:.2f}s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile_enable(False)
+    helm = s.helmholtz_residual(x)
+    del x
+    applies = sum(i["applies"] for i in infos)
+    value = applies * pts_per_apply / elapsed / 1e9
+    launch_us = prof["ms"] / prof["launches"] * 1e3
+    bytes_per_launch = prof["bytes"] / prof["launches"]
+    achieved = bytes_per_launch / (launch_us * 1e-6) / 1e9
+    kname = {"blocked_2d": "block_steps_kernel", "blocked_3d": "block3d_steps_kernel",
+             "node": "step_kernel"}.get(tun["kernel"], tun["kernel"])
+    del s
+    torch.cuda.empty_cache()
+    ceil = stream_ceilings(dev)
+    log(f"streaming kernel: {ceil}")
+    ub = unblocked_bytes(args.precision, True, False)
+    result = {
+        "metric": "grid-pt updates/s (GPts/s, % HBM roofline) + time to Helmholtz residual 1e-8",
+        "value": round(value, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic (seeded random inclusion and point-like Gaussian source)",
+        "config": {
+            "workload": f"cube {n}^3, order {order}, c = 1 with a c = 1.5 ball, omega = {w['omega']:g}, "
+                        f"point-like Gaussian source; {args.precision} state, FP64 filter and Krylov; "
+                        f"step = {args.iters} CG iterations (1/c^2 inner product) from v = 0",
+            "n": n, "order": order, "omega": w["omega"], "nt": tp["nt"], "solver": "cg",
+            "iterations_per_step": args.iters, "state_precision": args.precision,
+            "filter_and_krylov_precision": "fp64", "kernel": tun["kernel"], "steps_per_launch": tun["kblock"],
+            "tile_rows": tun["tile"], "owned_tile": list(tun["owned"]),
+        },
+        "time_to_residual_s": None,
+        "rel_res_after_step": infos[-1]["rel_res"],
+        "helmholtz_rel_res_after_step": helm,
+        "applies_per_step": infos[-1]["applies"],
+        "stepping_share": round(prof["ms"] * 1e-3 / elapsed, 4),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kname, {"n": n, "order": order, "precision": args.precision,
+                                                "kblock": tun["kblock"], "tile_rows": tun["tile"]}),
+            "bytes_per_launch": bytes_per_launch,
+            "launch_us": round(launch_us, 3),
+            "launches": prof["launches"],
+            "measured_copy_GBps": ceil["copy_GBps"],
+            "frac_of_measured_copy": round(achieved / ceil["copy_GBps"], 4),
+            "stream_kernel_GBps": ceil,
+            "kernel_GPts_per_s": round(prof["point_steps"] / prof["ms"] * 1e-6, 2),
+            "unblocked_bytes_per_point_step": ub,
+            "kernel_GPts_vs_unblocked_roofline": round(prof["point_steps"] / prof["ms"] * 1e-6 / (HBM_PEAK_GBS / ub),
+                                                       3),
+        },
+    }
+    if args.square:
+        log("2048^2 FP64 CG solve to 1e-8 (time to residual)")
+        result["square_fp64_time_to_residual"] = run_square_reference(dev)
+    if args.cpu_baseline:
+        steps = 24
+        log(f"CPU oracle baseline: {steps} leapfrog steps of the {n}^3 grid on the host cores")
+        rate, cores, sec = cpu_baseline_grid(3, n, order, w["c2"], w["omega"], steps)
+        steps1 = 5
+        rate1, _, sec1 = cpu_baseline_grid(3, n, order, w["c2"], w["omega"], steps1, threads=1)
+        result["cpu_baseline"] = {
+            "value": round(rate, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
+            "sample": f"W_h(v, 0) over {steps} leapfrog steps of the same {n}^3 grid, c^2 and time step "
+                      f"({unknowns} unknowns), FP64, {sec:.1f}s on {cores} threads",
+            "single_thread_value": round(rate1, 4),
+            "single_thread_sample": f"{steps1} leapfrog steps of the same grid on one thread, {sec1:.1f}s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+        }
+    print(json.dumps(result), flush=True)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "block_steps_kernel_square2048_p4_fp64_hbm_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_03074_amd", "csrc", "wh_block_impl.h")
+CSRC = os.path.join(ROOT, "paper_2504_03074_amd", "csrc")
+# committed rocprofv3 HBM-counter summaries: (summary file, kernel source it was taken from)
+COUNTER_SUMMARIES = {
+    "block_steps_kernel": (os.path.join(ROOT, "profiles", "block_steps_kernel_square2048_p4_fp64_hbm_counters.txt"),
+                           os.path.join(CSRC, "wh_block_impl.h")),
+    "block3d_steps_kernel": (os.path.join(ROOT, "profiles", "block3d_steps_kernel_cube512_p2_fp32_hbm_counters.txt"),
+                             os.path.join(CSRC, "wh_block3d_impl.h")),
+}
 
 
-def measured_traffic(n, precision, tun):
-    """HBM bytes per launch of the blocked kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
-    the workload differs from the one profiled or the kernel source changed
+def measured_traffic(kernel, match):
+    """HBM bytes per launch of `kernel` from its committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary's workload fields differ from `match` or the kernel source changed
     since the counters were taken."""
     import hashlib
-    if not (n == 2048 and precision == "fp64" and tun["kernel"] == "blocked_2d") or not os.path.exists(COUNTER_SUMMARY):
+    if kernel not in COUNTER_SUMMARIES:
         return None
-    keys = ("traffic_bytes_per_launch", "kernel_source_sha256", "kblock", "tile_rows")
+    summary, source = COUNTER_SUMMARIES[kernel]
+    if not os.path.exists(summary):
+        return None
     fields = {}
-    for line in open(COUNTER_SUMMARY):
-        if "=" in line and line.split("=")[0].strip() in keys:
+    for line in open(summary):
+        if "=" in line:
             k, v = line.split("=", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
         return None
-    if fields.get("kblock") != str(tun["kblock"]) or fields.get("tile_rows") != str(tun["tile"]):
+    if any(fields.get(k) != str(v) for k, v in match.items()):
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def stream_ceilings(dev, nbytes=1 << 30):
+    """GB/s of the library's streaming kernel: copy, read and write of
+    `nbytes`, each the average of 10 launches after one untimed."""
+    import torch
+    from paper_2504_03074_amd.wh import wh_stream_bandwidth
+    a = torch.zeros(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+        ms = wh_stream_bandwidth(kind, a.data_ptr(), b.data_ptr(), nbytes, 0, 10, stream)
+        out[f"{name}_GBps"] = round(moved / (ms * 1e-3) * 1e-9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w, order, nt_sample):
@@ -396,13 +619,26 @@ def cpu_single_thread(w, order, steps=12):
 
 
 def cpu_model():
+    """Model name of the host CPU with its family/model/stepping numbers (a
+    virtualised host may report only a short name) and the logical CPU count."""
+    name, fam, mod, step, logical = "unknown", "?", "?", "?", 0
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "processor":
+                logical += 1
+            elif key == "model name" and name == "unknown":
+                name = val
+            elif key == "cpu family" and fam == "?":
+                fam = val
+            elif key == "model" and mod == "?":
+                mod = val
+            elif key == "stepping" and step == "?":
+                step = val
     except OSError:
         pass
-    return "unknown"
+    return f"{name} (family {fam}, model {mod}, stepping {step}; {logical} logical CPUs in /proc/cpuinfo)"
 
 
 def run_batch(args, dev):
@@ -677,9 +913,14 @@ def main():
     if args.mode == "mixed":
         run_mixed(args, dev)
         return
+    if args.mode == "stream":
+        print(json.dumps({"mode": "stream", "bytes": 1 << 30, **stream_ceilings(dev)}), flush=True)
+        return
     if args.workload == "cube":
         if args.mode == "kernel":
             run_cube_kernel(args, dev)
+        elif args.iters > 0:
+            run_cube_block(args, dev)
         else:
             run_cube_solve(args, dev)
         return
@@ -796,15 +1037,20 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.n, args.precision, tun),
+            "traffic": measured_traffic(kname, {"n": args.n, "order": order, "precision": args.precision,
+                                                "kblock": tun["kblock"], "tile_rows": tun["tile"]}),
             "bytes_per_launch": bytes_per_launch,
             "launch_us": round(launch_us, 3),
             "launches": prof["launches"],
             "kernel_GPts_per_s": round(prof["point_steps"] / prof["ms"] * 1e-6, 2),
             # temporal blocking: the same rate against the one-step-per-pass
-            # roofline (56 B per point-step at 8 TB/s = 142.9 GPts/s)
+            # roofline of the timed applications (A v: no forcing, variable
+            # c^2: 3 state levels + c^2 + the FP64 accumulator read and
+            # written = 48 B per point-step in FP64, 166.7 GPts/s at 8 TB/s)
+            "unblocked_bytes_per_point_step": unblocked_bytes(args.precision, True, False),
             "kernel_GPts_vs_unblocked_roofline": round(prof["point_steps"] / prof["ms"] * 1e-6
-                                                       / (HBM_PEAK_GBS / 56.0), 3),
+                                                       / (HBM_PEAK_GBS / unblocked_bytes(args.precision, True,
+                                                                                          False)), 3),
         },
     }
     if args.cpu_baseline:
@@ -813,7 +1059,8 @@ def main():
         rate1, sec1, nt1 = cpu_single_thread(dict(w, n=args.n), order)
         result["cpu_baseline"] = {
             "value": round(rate, 4), "unit": "GPts/s", "cores": cores, "kind": "oracle",
-            "single_thread_value": round(rate1, 4), "cpu_model": cpu_model(),
+            "single_thread_value": round(rate1, 4), "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
             "single_thread_sample": f"{nt1} leapfrog steps of the same grid on one thread, {sec1:.1f}s",
             "sample": f"one W_h(v,0) application ({nt} leapfrog steps over {unknowns} unknowns) of the same "
                       f"workload, FP64, {sec:.1f}s; CPU time to residual extrapolated as "

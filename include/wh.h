@@ -339,6 +339,22 @@ WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
 /* Synchronise the stream and return the counters accumulated so far. */
 WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
 
+/* Streaming-bandwidth reference for reading rooflines (not part of the
+ * method): `reps` back-to-back launches of the library's own 16-byte-per-lane
+ * grid-stride kernel over `bytes` (a positive multiple of 16, 16-byte-aligned
+ * device buffers), after one untimed launch, timed with events on `stream`
+ * (a hipStream_t; NULL = null stream), which is synchronised.
+ *   kind 0  copy src -> dst (buffers must not overlap; 2 x bytes moved)
+ *   kind 1  read src (dst unused, may be NULL; bytes moved)
+ *   kind 2  write dst (src unused, may be NULL; bytes moved)
+ * groups = work-groups of 256 lanes (0 = 1024, the fastest copy measured on
+ * MI355X).  *ms_per_launch receives the average launch time.  Errors:
+ * WH_EINVAL for a bad kind, size, alignment, group count, repetition count
+ * (1..10000), overlap or a pointer that is not device memory; WH_EDEVICE if a
+ * launch or event call fails. */
+WH_API wh_status wh_stream_bandwidth(int32_t kind, const void *src, void *dst, size_t bytes, int32_t groups,
+                                     int32_t reps, void *stream, double *ms_per_launch);
+
 /* ------------------------------------------------------------------------
  * Deflation (Alg. 3, Sec. 5.2) with the eigenmodes of the unit box.
  *

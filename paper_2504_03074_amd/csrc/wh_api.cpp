@@ -1153,6 +1153,42 @@ wh_status wh_apply_A(wh_ctx *c, const double *v, double *Av) {
   return apply_impl(c, v, false, wh::FINAL_A, Av, nullptr);
 }
 
+wh_status wh_stream_bandwidth(int32_t kind, const void *src, void *dst, size_t bytes, int32_t groups, int32_t reps,
+                              void *stream, double *ms_per_launch) {
+  if (kind < 0 || kind > 2 || !ms_per_launch || reps < 1 || reps > 10000) return WH_EINVAL;
+  if (bytes < 16 || bytes % 16 != 0 || bytes > ((size_t)1 << 40)) return WH_EINVAL;
+  if (groups < 0 || groups > 65535) return WH_EINVAL;
+  if (kind != 2 && (!src || !is_device_ptr(src) || reinterpret_cast<uintptr_t>(src) % 16 != 0)) return WH_EINVAL;
+  if (kind != 1 && (!dst || !is_device_ptr(dst) || reinterpret_cast<uintptr_t>(dst) % 16 != 0)) return WH_EINVAL;
+  if (kind == 0 && static_cast<const char *>(src) < static_cast<const char *>(dst) + bytes &&
+      static_cast<const char *>(dst) < static_cast<const char *>(src) + bytes)
+    return WH_EINVAL;
+  const int g = groups > 0 ? groups : 1024;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return WH_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return WH_EDEVICE;
+  }
+  wh_status st = WH_OK;
+  float ms = 0.0f;
+  if (wh::launch_stream(kind, src, dst, (int64_t)bytes, g, nullptr, s) != hipSuccess ||
+      hipEventRecord(e0, s) != hipSuccess) {
+    st = WH_EDEVICE;
+  } else {
+    for (int r = 0; r < reps && st == WH_OK; ++r)
+      if (wh::launch_stream(kind, src, dst, (int64_t)bytes, g, nullptr, s) != hipSuccess) st = WH_EDEVICE;
+    if (st == WH_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = WH_EDEVICE;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == WH_OK) *ms_per_launch = (double)ms / reps;
+  return st;
+}
+
 wh_status wh_dot(wh_ctx *c, const double *x, const double *y, double *out) {
   WH_TRY(need(c, true, true, false, false, false));
   if (!out) return fail(c, WH_EINVAL, "out is NULL");

@@ -39,6 +39,11 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
                        const void *c2, const void *f, double gn, double wn, int mode,
                        const double *v, double *out, hipStream_t s);
 
+// Streaming-bandwidth reference kernel: kind 0 copy, 1 read, 2 write of
+// `bytes` (a multiple of 16) with `groups` work-groups of 256 lanes.
+hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, int groups, float *sink,
+                         hipStream_t s);
+
 // Temporally blocked steps for 2-D grids: ksteps <= K leapfrog steps per pass
 // over the grid (K fixes the halo K*p/2 and the tile shape).  in_prev/in_cur
 // hold W^{n-1}, W^n; out_prev/out_cur receive W^{n+ks-1}, W^{n+ks}.  gn[s],

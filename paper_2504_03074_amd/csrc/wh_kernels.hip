@@ -632,6 +632,30 @@ void dispatch_step(const StepGeom &g, const void *cur, void *prev_next, double *
   else step_typed<T, 3, 4>(g, cur, prev_next, acc, c2, f, gn, wn, mode, v, out, s);
 }
 
+// Streaming-bandwidth reference: 16-byte accesses per lane over a buffer,
+// grid-stride.  kind 0 copies src to dst, 1 reads src (the sum is kept live by
+// a store taken only for NaN data), 2 writes dst.
+typedef float stream_vec __attribute__((ext_vector_type(4)));
+template <int KIND>
+__global__ __launch_bounds__(256) void stream_kernel(const stream_vec *__restrict__ src, stream_vec *__restrict__ dst,
+                                                     int64_t n, float *__restrict__ sink) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  float acc = 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    if constexpr (KIND == 0) {
+      dst[i] = src[i];
+    } else if constexpr (KIND == 1) {
+      const stream_vec v = src[i];
+      acc += (v.x + v.y) + (v.z + v.w);
+    } else {
+      dst[i] = stream_vec{1.0f, 2.0f, 3.0f, 4.0f};
+    }
+  }
+  if constexpr (KIND == 1) {
+    if (acc != acc && sink) sink[0] = acc;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_first_step(bool fp32, const StepGeom &half, const double *v, void *W0, void *W1, double *acc,
@@ -700,6 +724,17 @@ hipError_t launch_from_state(bool fp32, const void *src, double *dst, int64_t n,
 hipError_t launch_set_walls(bool fp32, const StepGeom &g, void *a, double value, hipStream_t s) {
   if (fp32) set_walls_kernel<float><<<flat_blocks(g.nodes), 256, 0, s>>>(g, static_cast<float *>(a), (float)value);
   else set_walls_kernel<double><<<flat_blocks(g.nodes), 256, 0, s>>>(g, static_cast<double *>(a), value);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, int groups, float *sink,
+                         hipStream_t s) {
+  const int64_t n = bytes / 16;
+  const stream_vec *a = static_cast<const stream_vec *>(src);
+  stream_vec *b = static_cast<stream_vec *>(dst);
+  if (kind == 0) stream_kernel<0><<<groups, 256, 0, s>>>(a, b, n, sink);
+  else if (kind == 1) stream_kernel<1><<<groups, 256, 0, s>>>(a, b, n, sink);
+  else stream_kernel<2><<<groups, 256, 0, s>>>(a, b, n, sink);
   return hipGetLastError();
 }
 

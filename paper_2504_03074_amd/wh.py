@@ -107,6 +107,8 @@ def _load():
                                 ctypes.POINTER(wh_solve_info)]),
         "wh_helmholtz_residual": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
         "wh_dot": (st, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+        "wh_stream_bandwidth": (st, [ctypes.c_int32, _vp, _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                     _vp, ctypes.POINTER(ctypes.c_double)]),
         "wh_set_tuning": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "wh_get_tuning": (st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -310,6 +312,19 @@ def wh_dot(ctx, x: int, y: int) -> float:
     out = ctypes.c_double()
     _check(ctx, _load().wh_dot(ctx, _vp(x), _vp(y), ctypes.byref(out)))
     return float(out.value)
+
+
+def wh_stream_bandwidth(kind: int, src: int, dst: int, nbytes: int, groups: int = 0, reps: int = 10,
+                        stream: int = 0) -> float:
+    """Average milliseconds per launch of the library's streaming kernel
+    (kind 0 copy, 1 read, 2 write) over `nbytes` of device memory."""
+    ms = ctypes.c_double()
+    st = _load().wh_stream_bandwidth(int(kind), _vp(src) if src else None, _vp(dst) if dst else None,
+                                     int(nbytes), int(groups), int(reps), _vp(stream) if stream else None,
+                                     ctypes.byref(ms))
+    if st != 0:
+        raise WhError(st, "wh_stream_bandwidth rejected its arguments or a launch failed")
+    return float(ms.value)
 
 
 def wh_set_tuning(ctx, kernel=WH_KERNEL_AUTO, kblock=0, tile=0):
