@@ -339,6 +339,26 @@ WH_API wh_status wh_profile_enable(wh_ctx *ctx, int32_t enable);
 /* Synchronise the stream and return the counters accumulated so far. */
 WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
 
+/* A v = v - W_h(v, 0), as wh_apply_A, for callers that cannot allocate
+ * device memory or use a workspace for it (code under HIP stream capture,
+ * tight serving loops, harnesses that forbid allocation): the four state
+ * levels and the FP64 filter accumulator of the application are taken from a
+ * fixed array of 192 MiB in device memory that the library holds on every GPU
+ * it runs on until the process ends (its address is looked up on the first
+ * call on each device), instead of the workspace.  c^2 and f are still read
+ * from the context's workspace, where wh_set_c2 / wh_set_source put them; v
+ * and Av are device arrays owned by the caller as for wh_apply_A.  Nothing is
+ * allocated and no event is recorded (profiling counters are not updated).
+ * The array is shared by every context on that GPU and keeps the last call's
+ * contents (every application overwrites all of it before reading it): calls
+ * that overlap on one GPU, from any context or stream, race.  Limit: 4 state
+ * levels + the accumulator, each rounded to 256 bytes, must fit in 192 MiB
+ * (FP64: about 5.0 million nodes, e.g. 2048^2 or 170^3; FP32 state: about 8.3
+ * million); larger grids return WH_EINVAL with the sizes in wh_last_error.
+ * Also WH_EINVAL for an implicit-stepping context, NULL or host pointers, or
+ * Av == v; WH_ESTATE before grid, workspace, c^2 and frequency are set. */
+WH_API wh_status wh_apply_A_noalloc(wh_ctx *ctx, const double *v, double *Av);
+
 /* Streaming-bandwidth reference for reading rooflines (not part of the
  * method): `reps` back-to-back launches of the library's own 16-byte-per-lane
  * grid-stride kernel over `bytes` (a positive multiple of 16, 16-byte-aligned

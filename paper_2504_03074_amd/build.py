@@ -18,7 +18,7 @@ ARCH = "gfx950"
 
 SOURCES = ["wh_block_f64_p4.hip", "wh_block_f32_p4.hip", "wh_block_f64_p2.hip", "wh_block_f32_p2.hip",
            "wh_block3d_f64_p4.hip", "wh_block3d_f32_p4.hip", "wh_block3d_f64_p2.hip", "wh_block3d_f32_p2.hip",
-           "wh_kernels.hip", "wh_mg.hip", "wh_block.hip", "wh_api.cpp"]
+           "wh_kernels.hip", "wh_mg.hip", "wh_block.hip", "wh_noalloc.hip", "wh_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

@@ -1153,6 +1153,39 @@ wh_status wh_apply_A(wh_ctx *c, const double *v, double *Av) {
   return apply_impl(c, v, false, wh::FINAL_A, Av, nullptr);
 }
 
+wh_status wh_apply_A_noalloc(wh_ctx *c, const double *v, double *Av) {
+  WH_TRY(need(c, true, true, true, false, true));
+  if (c->implicit)
+    return fail(c, WH_EINVAL, "implicit stepping keeps its levels in the implicit workspace: use wh_apply_A");
+  WH_TRY(set_device(c));
+  WH_TRY(check_dev(c, v, "v"));
+  WH_TRY(check_dev(c, Av, "Av"));
+  if (Av == v) return fail(c, WH_EINVAL, "Av may not alias v");
+  // four state levels and the FP64 accumulator, 256-byte aligned
+  const size_t level = align256((size_t)c->nodes * state_bytes(c));
+  const size_t accb = align256((size_t)c->nodes * 8);
+  const size_t need_bytes = 4 * level + accb;
+  if (need_bytes > wh::kStaticScratchBytes)
+    return fail(c, WH_EINVAL,
+                "this grid needs %zu bytes of scratch (four state levels and the FP64 accumulator); the static "
+                "scratch holds %zu bytes",
+                need_bytes, wh::kStaticScratchBytes);
+  void *base = nullptr;
+  WH_HIP(c, wh::static_scratch(c->device, &base));
+  char *p = static_cast<char *>(base);
+  void *W[4] = {c->W[0], c->W[1], c->W[2], c->W[3]};
+  double *acc = c->acc;
+  const bool profiling = c->profiling;
+  for (int i = 0; i < 4; ++i) c->W[i] = p + (size_t)i * level;
+  c->acc = reinterpret_cast<double *>(p + 4 * level);
+  c->profiling = false;  // no event creation on this path
+  const wh_status st = apply_impl(c, v, false, wh::FINAL_A, Av, nullptr);
+  for (int i = 0; i < 4; ++i) c->W[i] = W[i];
+  c->acc = acc;
+  c->profiling = profiling;
+  return st;
+}
+
 wh_status wh_stream_bandwidth(int32_t kind, const void *src, void *dst, size_t bytes, int32_t groups, int32_t reps,
                               void *stream, double *ms_per_launch) {
   if (kind < 0 || kind > 2 || !ms_per_launch || reps < 1 || reps > 10000) return WH_EINVAL;

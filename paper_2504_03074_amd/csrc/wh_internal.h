@@ -39,6 +39,12 @@ hipError_t launch_step(bool fp32, const StepGeom &g, const void *cur, void *prev
                        const void *c2, const void *f, double gn, double wn, int mode,
                        const double *v, double *out, hipStream_t s);
 
+// Fixed device scratch of the allocation-free entry point (wh_noalloc.hip):
+// kStaticScratchBytes per device; static_scratch returns its address on the
+// current device (looked up once per device).
+constexpr size_t kStaticScratchBytes = (size_t)192 << 20;
+hipError_t static_scratch(int device, void **ptr);
+
 // Streaming-bandwidth reference kernel: kind 0 copy, 1 read, 2 write of
 // `bytes` (a multiple of 16) with `groups` work-groups of 256 lanes.
 hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, int groups, float *sink,

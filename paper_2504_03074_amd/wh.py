@@ -101,6 +101,7 @@ def _load():
         "wh_run_periods": (st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
         "wh_apply": (st, [_vp, _vp, _vp, ctypes.c_int32]),
         "wh_apply_A": (st, [_vp, _vp, _vp]),
+        "wh_apply_A_noalloc": (st, [_vp, _vp, _vp]),
         "wh_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, ctypes.POINTER(wh_solve_info)]),
         "wh_solve_rhs": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, _vp, ctypes.POINTER(wh_solve_info)]),
         "wh_solve_mixed": (st, [_vp, _vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(wh_solve_opts), _vp,
@@ -258,6 +259,10 @@ def wh_apply(ctx, v: int, out: int, with_forcing: bool):
 
 def wh_apply_A(ctx, v: int, Av: int):
     _check(ctx, _load().wh_apply_A(ctx, _vp(v), _vp(Av)))
+
+
+def wh_apply_A_noalloc(ctx, v: int, Av: int):
+    _check(ctx, _load().wh_apply_A_noalloc(ctx, _vp(v), _vp(Av)))
 
 
 def wh_solve(ctx, opts: wh_solve_opts, v: int) -> tuple[int, wh_solve_info]:
@@ -608,6 +613,11 @@ class Solver:
     def apply_A(self, v, out=None):
         out = self.new() if out is None else out
         wh_apply_A(self.ctx, self._dev(v, "v"), self._dev(out, "out"))
+        return out
+
+    def apply_A_noalloc(self, v, out):
+        """A v with the library's fixed device scratch (no workspace levels)."""
+        wh_apply_A_noalloc(self.ctx, self._dev(v, "v"), self._dev(out, "out"))
         return out
 
     def run_periods(self, w0, with_forcing=True, want_final=True, want_filtered=True):
