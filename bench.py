@@ -35,6 +35,10 @@ Other modes (used to produce the committed rocprofv3 summaries):
                   iterations, so the target is not reached within one run);
                   prints progress every 200 iterations and one JSON line
   --mode stream   the library's streaming kernel (copy, read, write of 1 GiB)
+  --mode spectrum why the cube's CG solve is long: closed-form extreme
+                  eigenvalues of A for the constant-c cube, FP64 CG at 256^3
+                  (omega = 40) to the target and at 512^3 for --maxit
+                  iterations with Ritz estimates and true/recursive residuals
   --mode copy     a plain device copy of known size (HBM counter calibration)
   --mode batch    64 independent 2-D solves (grids 256^2, 512^2, 1024^2,
                   omega ~ U[20, 150], c = 1, 2nd order, Gaussian sources)
@@ -90,7 +94,8 @@ def parse():
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
-    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "stream", "batch", "adjoint", "implicit", "mixed"],
+    ap.add_argument("--mode", choices=["solve", "kernel", "copy", "stream", "batch", "adjoint", "implicit", "mixed",
+                                       "spectrum"],
                     default="solve")
     ap.add_argument("--nits", type=int, default=10, help="--mode implicit: implicit steps per period")
     ap.add_argument("--sizes", default="256,512,1024,2048", help="--mode implicit: grid sizes compared")
@@ -113,7 +118,7 @@ def parse():
         block = args.mode == "solve" and args.iters > 0
         args.precision = "fp32" if cube and (args.mode == "kernel" or block) else "fp64"
     if not args.maxit:
-        args.maxit = 2000 if cube else 40000
+        args.maxit = 2000 if cube else (6000 if args.mode == "spectrum" else 40000)
     if not args.order:
         args.order = 2 if cube else 4
     if not args.n:
@@ -531,6 +536,68 @@ def run_cube_block(args, dev):
     print(json.dumps(result), flush=True)
 
 
+def run_spectrum(args, dev):
+    """Why the 512^3 cube's CG solve is long: the closed-form extreme
+    eigenvalues of A = I - S_h over the sine modes of the constant-c cube
+    (background c = 1 and the inclusion's c = 1.5) at 256^3 (omega = 40) and
+    512^3 (omega = 80), the same points per wavelength; FP64 CG on the
+    inclusion cube at 256^3 to the residual target and at 512^3 for --maxit
+    iterations, each with the extreme Ritz values of its Lanczos matrix
+    (estimates of A's extreme eigenvalues) and the true against the recursive
+    residual at exit; and the iteration count at 512^3 predicted from them."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    out = {"mode": "spectrum"}
+    for n, omega, maxit in ((256, 40.0, 40000), (512, 80.0, args.maxit)):
+        w = wl.cube_inclusion(n=n, order=2, omega=omega)
+        s = Solver(3, (n, n, n), order=2, precision="fp64", restart=2)
+        s.set_c2(w["c2"])
+        s.set_source(w["f"])
+        tp = s.set_frequency(w["omega"])
+        del w
+        rec = {"n": n, "omega": omega, "nt": tp["nt"]}
+        for c2 in (1.0, 2.25):
+            t0 = time.perf_counter()
+            lo, hi, k = s.filter_spectrum(c2)
+            rec[f"closed_form_c2_{c2:g}"] = {"a_min": lo, "a_max": hi, "kappa": hi / lo, "mode_at_min": k,
+                                              "seconds": round(time.perf_counter() - t0, 2)}
+            log(f"{n}^3 omega {omega}: c^2 = {c2:g}: 1 - beta_d in [{lo:.3e}, {hi:.3f}], kappa {hi / lo:.3e}, "
+                f"closest mode {k}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = []
+
+        def progress(kk, rel):
+            if kk % 500 == 0:
+                hist.append((kk, rel))
+                log(f"  {n}^3 iteration {kk}: relative residual {rel:.3e} after {time.perf_counter() - t0:.1f}s")
+
+        x, info = s.solve(method="cg", rtol=args.rtol, maxit=maxit, callback=progress)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec["cg"] = {"iterations": info["iters"], "converged": bool(info["converged"]), "seconds": round(t, 2),
+                     "ms_per_iteration": round(t / max(info["iters"], 1) * 1e3, 2),
+                     "rel_res_true": info["rel_res"], "rel_res_recursive": info["rel_res_recursive"],
+                     "ritz_min": info["ritz_min"], "ritz_max": info["ritz_max"],
+                     "kappa_ritz": info["ritz_max"] / info["ritz_min"], "history": hist[-40:],
+                     "helmholtz_rel_res": s.helmholtz_residual(x)}
+        log(f"{n}^3: {info['iters']} iterations, true {info['rel_res']:.3e}, recursive "
+            f"{info['rel_res_recursive']:.3e}, Ritz [{info['ritz_min']:.3e}, {info['ritz_max']:.3f}]")
+        out[f"cube{n}"] = rec
+        del s, x
+        torch.cuda.empty_cache()
+    # CG needs about sqrt(kappa)/2 ln(2/eps) iterations; scale the iteration
+    # count measured at 256^3 by the ratio of the two Ritz estimates
+    a, b = out["cube256"]["cg"], out["cube512"]["cg"]
+    if a["converged"]:
+        pred = a["iterations"] * math.sqrt(b["kappa_ritz"] / a["kappa_ritz"])
+        out["predicted_iterations_512"] = round(pred)
+        out["predicted_time_to_residual_512_s_extrapolated"] = round(pred * b["ms_per_iteration"] * 1e-3, 1)
+    out["bound_iterations_512"] = round(0.5 * math.sqrt(b["kappa_ritz"]) * math.log(2.0 / args.rtol))
+    print(json.dumps(out), flush=True)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -915,6 +982,9 @@ def main():
         return
     if args.mode == "stream":
         print(json.dumps({"mode": "stream", "bytes": 1 << 30, **stream_ceilings(dev)}), flush=True)
+        return
+    if args.mode == "spectrum":
+        run_spectrum(args, dev)
         return
     if args.workload == "cube":
         if args.mode == "kernel":

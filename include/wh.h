@@ -139,7 +139,15 @@ typedef struct {
  *               constant c^2; NaN when c^2 varies
  *   seconds     wall time of the call
  *   bnorm       ||b||_2 with b = W_h(0, f)
- *   point_steps interior-node time steps executed */
+ *   point_steps interior-node time steps executed
+ *   rel_res_recursive  CG: the residual norm its recursion carried at exit
+ *               (/ ||b||), beside the true rel_res recomputed from b - A v
+ *               (their gap shows rounding drift); NaN for FPI and GMRES
+ *   ritz_min, ritz_max  CG: the extreme eigenvalues of the Lanczos
+ *               tridiagonal built from CG's step lengths and residual ratios
+ *               over its longest stretch between restarts: estimates of the extreme
+ *               eigenvalues of A = I - S_h (1/c^2-weighted inner product);
+ *               ritz_max / ritz_min estimates kappa(A).  NaN for FPI/GMRES */
 typedef struct {
   int32_t iters;
   int32_t applies;
@@ -152,6 +160,9 @@ typedef struct {
   double seconds;
   double bnorm;
   double point_steps;
+  double rel_res_recursive;
+  double ritz_min;
+  double ritz_max;
 } wh_solve_info;
 
 #define WH_MAX_RESTART 4096
@@ -358,6 +369,21 @@ WH_API wh_status wh_profile_read(wh_ctx *ctx, wh_profile *out);
  * Also WH_EINVAL for an implicit-stepping context, NULL or host pointers, or
  * Av == v; WH_ESTATE before grid, workspace, c^2 and frequency are set. */
 WH_API wh_status wh_apply_A_noalloc(wh_ctx *ctx, const double *v, double *Av);
+
+/* Diagnostic (host only, no device work): the extreme eigenvalues of
+ * A = I - S_h over all sine modes of the unit box (Sec. 5.3: S_h has the
+ * eigenvalues beta_d(lambda~) of the discrete filter, Sec. 4.2.1 and App.
+ * A.3) for a constant wave speed c2 (> 0) under the context's grid, order
+ * and time parameters (wh_set_frequency must have been called; the context's
+ * own c^2 is not used, so a variable-c^2 context can be probed with its
+ * background value).  *a_min = min (1 - beta_d), *a_max = max (1 - beta_d):
+ * a_max / a_min is the condition number of A for that c2; k_min (nullable,
+ * 3 int32, 0 for the unused axis) receives the wave numbers of the mode
+ * closest to resonance.  Spreads the (n_x-1)(n_y-1)(n_z-1) mode evaluations
+ * over the host's hardware threads (up to 2^31 modes).  WH_EINVAL for NULL
+ * outputs or a bad c2, WH_EUNSTABLE if c2 puts a mode beyond the stability
+ * limit of the context's dt, WH_ESTATE before grid and frequency are set. */
+WH_API wh_status wh_filter_spectrum(wh_ctx *ctx, double c2, double *a_min, double *a_max, int32_t *k_min);
 
 /* Streaming-bandwidth reference for reading rooflines (not part of the
  * method): `reps` back-to-back launches of the library's own 16-byte-per-lane

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "wh.h"
@@ -1186,6 +1187,68 @@ wh_status wh_apply_A_noalloc(wh_ctx *c, const double *v, double *Av) {
   return st;
 }
 
+wh_status wh_filter_spectrum(wh_ctx *c, double c2, double *a_min, double *a_max, int32_t *k_min) {
+  WH_TRY(need(c, true, false, false, false, true));
+  if (!a_min || !a_max) return fail(c, WH_EINVAL, "a_min and a_max must not be NULL");
+  if (!(c2 > 0.0) || !std::isfinite(c2)) return fail(c, WH_EINVAL, "c2 must be finite and > 0");
+  double modes = 1.0;
+  for (int m = 0; m < c->dim; ++m) modes *= (double)(c->n[m] - 1);
+  if (modes > (double)((int64_t)1 << 31)) return fail(c, WH_EINVAL, "more than 2^31 modes");
+  std::vector<double> ax[3];
+  for (int m = 0; m < c->dim; ++m)
+    for (int64_t k = 1; k < c->n[m]; ++k) ax[m].push_back(axis_eigenvalue(c->order, c->n[m], k));
+  const size_t nz = c->dim == 3 ? ax[2].size() : 1;
+  unsigned nthreads = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+  struct Part {
+    double lo = INFINITY, hi = -INFINITY;
+    int32_t k[3] = {0, 0, 0};
+    bool unstable = false;
+  };
+  std::vector<Part> parts(nthreads);
+  auto work = [&](unsigned t) {
+    Part &pt = parts[t];
+    for (size_t kz = t; kz < nz; kz += nthreads)
+      for (size_t ky = 0; ky < ax[1].size(); ++ky)
+        for (size_t kx = 0; kx < ax[0].size(); ++kx) {
+          const double lam2 = c2 * (ax[0][kx] + ax[1][ky] + (c->dim == 3 ? ax[2][kz] : 0.0));
+          const double a = 1.0 - mode_beta(c, lam2);
+          if (!std::isfinite(a)) {
+            pt.unstable = true;
+            continue;
+          }
+          if (a < pt.lo) {
+            pt.lo = a;
+            pt.k[0] = (int32_t)kx + 1;
+            pt.k[1] = (int32_t)ky + 1;
+            pt.k[2] = c->dim == 3 ? (int32_t)kz + 1 : 0;
+          }
+          pt.hi = std::max(pt.hi, a);
+        }
+  };
+  try {
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool) th.join();
+  } catch (const std::exception &) {
+    return fail(c, WH_ENOMEM, "could not start host threads");
+  }
+  Part all;
+  for (const Part &pt : parts) {
+    all.unstable |= pt.unstable;
+    all.hi = std::max(all.hi, pt.hi);
+    if (pt.lo < all.lo) {
+      all.lo = pt.lo;
+      std::memcpy(all.k, pt.k, sizeof all.k);
+    }
+  }
+  if (all.unstable) return fail(c, WH_EUNSTABLE, "c2 = %g puts modes beyond the stability limit of dt", c2);
+  *a_min = all.lo;
+  *a_max = all.hi;
+  if (k_min) std::memcpy(k_min, all.k, sizeof all.k);
+  return WH_OK;
+}
+
 wh_status wh_stream_bandwidth(int32_t kind, const void *src, void *dst, size_t bytes, int32_t groups, int32_t reps,
                               void *stream, double *ms_per_launch) {
   if (kind < 0 || kind > 2 || !ms_per_launch || reps < 1 || reps > 10000) return WH_EINVAL;
@@ -1599,6 +1662,54 @@ static wh_status solve_gmres(wh_ctx *c, const wh_solve_opts *o, double *x, wh_so
   return st;
 }
 
+// Extreme eigenvalues of the symmetric tridiagonal matrix that CG's step
+// lengths alpha_j and residual ratios beta_j define (the Lanczos matrix of
+// the Krylov space CG has built): T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+// T_j,j+1 = sqrt(beta_j)/alpha_j.  Bisection on Sturm counts.
+static void lanczos_extremes(const std::vector<double> &alpha, const std::vector<double> &beta, double *lo,
+                             double *hi) {
+  const size_t m = alpha.size();
+  *lo = *hi = NAN;
+  if (m == 0) return;
+  std::vector<double> d(m), e(m > 1 ? m - 1 : 0);
+  for (size_t j = 0; j < m; ++j) d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+  for (size_t j = 0; j + 1 < m; ++j) e[j] = std::sqrt(beta[j]) / alpha[j];
+  double glo = INFINITY, ghi = -INFINITY;
+  for (size_t j = 0; j < m; ++j) {
+    const double r = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < m ? std::fabs(e[j]) : 0.0);
+    glo = std::min(glo, d[j] - r);
+    ghi = std::max(ghi, d[j] + r);
+  }
+  if (!std::isfinite(glo) || !std::isfinite(ghi)) return;
+  // number of eigenvalues below x
+  auto below = [&](double x) {
+    size_t cnt = 0;
+    double q = d[0] - x;
+    if (q < 0.0) ++cnt;
+    for (size_t j = 1; j < m; ++j) {
+      if (q == 0.0) q = 1e-300;
+      q = d[j] - x - e[j - 1] * e[j - 1] / q;
+      if (q < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  double a = glo, b = ghi;
+  for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+    const double mid = 0.5 * (a + b);
+    if (below(mid) >= 1) b = mid;
+    else a = mid;
+  }
+  *lo = 0.5 * (a + b);
+  a = glo;
+  b = ghi;
+  for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+    const double mid = 0.5 * (a + b);
+    if (below(mid) >= m) b = mid;
+    else a = mid;
+  }
+  *hi = 0.5 * (a + b);
+}
+
 // Conjugate gradients on A v = b in the inner product <u, w> = sum u w / c^2.
 // Iteration k keeps <r, r>_w and ||r||^2 in device slot (k & 1); the update
 // kernels read their coefficients from device memory, so each iteration
@@ -1638,9 +1749,11 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
     return WH_OK;
   };
 
-  double rel = 0.0, rel0 = -1.0;
+  double rel = 0.0, rel0 = -1.0, rel_rec = NAN;
   int64_t k = 0;
   wh_status st = WH_OK;
+  // CG's coefficients since the last restart (the Lanczos matrix)
+  std::vector<double> alphas, betas, best_a, best_b;
   WH_TRY(restart(k, &rel));
   rel0 = rel;
   while (bnorm > 0.0 && rel > o->rtol && k < o->maxit) {
@@ -1667,15 +1780,27 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
       break;
     }
     rel = bnorm > 0.0 ? std::sqrt(ee) / bnorm : 0.0;
+    rel_rec = rel;
+    alphas.push_back(sc[cur] / pq);
+    betas.push_back(sc[nxt] / sc[cur]);
     if (o->on_iter) o->on_iter((int32_t)k, rel, o->user);
     if (rel <= o->rtol) {
       // confirm with the true residual; continue from it if rounding drifted
       WH_TRY(restart(k, &rel));
       if (rel <= o->rtol) break;
+      // a restart begins a new Lanczos sequence; keep the longest one
+      if (alphas.size() > best_a.size()) {
+        best_a.swap(alphas);
+        best_b.swap(betas);
+      }
+      alphas.clear();
+      betas.clear();
       continue;
     }
     WH_HIP(c, wh::launch_xpay(r, p, c->scal + nxt, c->scal + cur, N, c->stream));
   }
+  // stopped by maxit: report the true residual beside the recursive one
+  if (st == WH_OK && bnorm > 0.0 && rel > o->rtol && k > 0) WH_TRY(restart(k, &rel));
   if (st == WH_OK) WH_TRY(defl_inflate(c, x));
   WH_HIP(c, hipStreamSynchronize(c->stream));
   if (info) {
@@ -1688,6 +1813,13 @@ static wh_status solve_cg(wh_ctx *c, const wh_solve_opts *o, double *x, wh_solve
     info->cr_avg = info->cr_last;
     info->ecr = std::pow(info->cr_avg, 1.0 / c->tp.periods);
     info->point_steps = applies * point_steps_per_apply(c);
+    info->rel_res_recursive = rel_rec;
+    if (best_a.size() > alphas.size()) {
+      alphas.swap(best_a);
+      betas.swap(best_b);
+    }
+    if (!betas.empty()) betas.pop_back();  // beta_k only couples to a step not taken
+    lanczos_extremes(alphas, betas, &info->ritz_min, &info->ritz_max);
   }
   if (st == WH_OK && rel > o->rtol)
     st = fail(c, WH_ENOTCONV, "CG reached maxit = %d at relative residual %g", o->maxit, rel);
@@ -1732,6 +1864,7 @@ static wh_status solve_dispatch(wh_ctx *c, const wh_solve_opts *o, const double 
   if (info) {
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->mu_pred = predicted_rate(c);
+    if (o->method != WH_SOLVER_CG) info->rel_res_recursive = info->ritz_min = info->ritz_max = NAN;
   }
   return st;
 }
@@ -1766,6 +1899,9 @@ wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, con
       hi->tp.alpha != lo->tp.alpha)
     return fail(hi, WH_EINVAL, "the two contexts must use the same time parameters");
   if (hi->ws_restart < 2) return fail(hi, WH_ENOMEM, "the outer context needs a workspace sized for restart >= 2");
+  if (hi->defl_count > 0 || lo->defl_count > 0)
+    return fail(hi, WH_EINVAL, "residual correction does not deflate: call wh_set_deflation with count 0 on both "
+                               "contexts first");
   WH_TRY(set_device(hi));
   WH_TRY(check_dev(hi, v, "v"));
   if (info) std::memset(info, 0, sizeof *info);
@@ -1825,6 +1961,7 @@ wh_status wh_solve_mixed(wh_ctx *hi, wh_ctx *lo, const wh_solve_opts *outer, con
     info->point_steps = applies_hi * point_steps_per_apply(hi) + applies_lo * point_steps_per_apply(lo);
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->mu_pred = predicted_rate(hi);
+    info->rel_res_recursive = info->ritz_min = info->ritz_max = NAN;
   }
   (void)inner_iters;
   if (st == WH_OK && rel > outer->rtol)
@@ -2802,6 +2939,7 @@ wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, 
     in.scaled_res = rel[i] * bnorm[i] / std::sqrt((double)c->nodes);
     in.cr_last = in.cr_avg = in.ecr = NAN;
     in.mu_pred = NAN;
+    in.rel_res_recursive = in.ritz_min = in.ritz_max = NAN;
     in.seconds = secs;
     in.point_steps = applies[i] * point_steps_per_apply(c);
   }

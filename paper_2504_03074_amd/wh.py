@@ -52,7 +52,9 @@ class wh_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("applies", ctypes.c_int32), ("rel_res", ctypes.c_double),
                 ("scaled_res", ctypes.c_double), ("cr_last", ctypes.c_double), ("cr_avg", ctypes.c_double),
                 ("ecr", ctypes.c_double), ("mu_pred", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("bnorm", ctypes.c_double), ("point_steps", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("point_steps", ctypes.c_double),
+                ("rel_res_recursive", ctypes.c_double), ("ritz_min", ctypes.c_double),
+                ("ritz_max", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,6 +104,8 @@ def _load():
         "wh_apply": (st, [_vp, _vp, _vp, ctypes.c_int32]),
         "wh_apply_A": (st, [_vp, _vp, _vp]),
         "wh_apply_A_noalloc": (st, [_vp, _vp, _vp]),
+        "wh_filter_spectrum": (st, [_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
         "wh_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, ctypes.POINTER(wh_solve_info)]),
         "wh_solve_rhs": (st, [_vp, ctypes.POINTER(wh_solve_opts), _vp, _vp, ctypes.POINTER(wh_solve_info)]),
         "wh_solve_mixed": (st, [_vp, _vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(wh_solve_opts), _vp,
@@ -259,6 +263,14 @@ def wh_apply(ctx, v: int, out: int, with_forcing: bool):
 
 def wh_apply_A(ctx, v: int, Av: int):
     _check(ctx, _load().wh_apply_A(ctx, _vp(v), _vp(Av)))
+
+
+def wh_filter_spectrum(ctx, c2: float):
+    """(min, max) of 1 - beta_d over the sine modes for constant c2, and the
+    wave numbers of the mode closest to resonance."""
+    lo, hi, k = ctypes.c_double(), ctypes.c_double(), (ctypes.c_int32 * 3)()
+    _check(ctx, _load().wh_filter_spectrum(ctx, float(c2), ctypes.byref(lo), ctypes.byref(hi), k))
+    return float(lo.value), float(hi.value), tuple(int(x) for x in k)
 
 
 def wh_apply_A_noalloc(ctx, v: int, Av: int):
@@ -614,6 +626,11 @@ class Solver:
         out = self.new() if out is None else out
         wh_apply_A(self.ctx, self._dev(v, "v"), self._dev(out, "out"))
         return out
+
+    def filter_spectrum(self, c2=1.0):
+        """(min, max) of 1 - beta_d over the sine modes for constant c2 and the
+        mode closest to resonance (host computation)."""
+        return wh_filter_spectrum(self.ctx, c2)
 
     def apply_A_noalloc(self, v, out):
         """A v with the library's fixed device scratch (no workspace levels)."""
