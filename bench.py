@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--solver", choices=["cg", "gmres"], default="cg")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--ref-rtol", dest="ref_rtol", type=float, default=1e-13,
+                    help="--mode mixed: tolerance of the FP64 reference solve")
     ap.add_argument("--maxit", type=int, default=0,
                     help="iteration cap of a solve to the residual target (0: 40000 square, 2000 cube)")
     ap.add_argument("--iters", type=int, default=100,
@@ -163,15 +165,34 @@ def run_mixed(args, dev):
     torch.cuda.synchronize()
     tm = time.perf_counter() - t0
     log(f"mixed: {im['iters']} corrections, {im['applies']} applies, {tm:.2f}s")
+    # calibration: an FP64 solve tight enough that kappa_hat * rtol is far
+    # below 1e-5 (kappa_hat from the extreme Ritz values of that solve), the
+    # reference against which each solve's error is reported
+    t0 = time.perf_counter()
+    xr, ir = hi.solve(method="cg", rtol=args.ref_rtol, maxit=4 * args.maxit)
+    torch.cuda.synchronize()
+    tr = time.perf_counter() - t0
+    kappa = ir["ritz_max"] / ir["ritz_min"]
+    log(f"FP64 reference CG to {args.ref_rtol:g}: {ir['iters']} iterations, {tr:.2f}s, kappa_hat {kappa:.3e}")
+
+    def err(x):
+        return float(torch.linalg.vector_norm(x - xr) / torch.linalg.vector_norm(xr))
+
     diff = float(torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64))
     print(json.dumps({"mode": "mixed", "workload": f"square {args.n}^2, order 4, random c^2 in [0.5,2], omega=200",
                       "kernel_GPts_per_s": rates,
                       "fp64_cg": {"seconds": round(t64, 3), "iters": i64["iters"], "applies": i64["applies"],
                                   "rel_res": i64["rel_res"], "converged": i64["converged"],
-                                  "helmholtz_rel_res": hi.helmholtz_residual(x64)},
+                                  "helmholtz_rel_res": hi.helmholtz_residual(x64), "rel_err_to_reference": err(x64)},
                       "mixed": {"seconds": round(tm, 3), "corrections": im["iters"], "applies": im["applies"],
                                 "rel_res": im["rel_res"], "converged": im["converged"],
-                                "helmholtz_rel_res": hi.helmholtz_residual(xm), "rel_diff_to_fp64": diff}}),
+                                "helmholtz_rel_res": hi.helmholtz_residual(xm), "rel_diff_to_fp64": diff,
+                                "rel_err_to_reference": err(xm)},
+                      "fp64_reference": {"rtol": args.ref_rtol, "seconds": round(tr, 3), "iters": ir["iters"],
+                                         "rel_res": ir["rel_res"], "converged": ir["converged"],
+                                         "ritz_min": ir["ritz_min"], "ritz_max": ir["ritz_max"],
+                                         "kappa_hat": kappa, "kappa_hat_times_rtol": kappa * args.ref_rtol,
+                                         "kappa_hat_times_target": kappa * args.rtol}}),
           flush=True)
 
 

@@ -333,6 +333,32 @@ __global__ __launch_bounds__(kRedThreads) void mdot_kernel(const double *__restr
   if (threadIdx.x == 0) partials[(int64_t)vec * nb + blockIdx.x] = s;
 }
 
+// Dots of w with up to kMdotGroup basis vectors per block row: w is read
+// once per group instead of once per vector (Arnoldi's Gram-Schmidt pass).
+constexpr int kMdotGroup = 8;
+template <int G>
+__global__ __launch_bounds__(kRedThreads) void mdot_group_kernel(const double *__restrict__ V, int64_t ldv, int k,
+                                                                 const double *__restrict__ w, int64_t n,
+                                                                 double *__restrict__ partials, int nb) {
+  __shared__ double sm[4];
+  const int v0 = blockIdx.y * G;
+  double s[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) s[g] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; e < n; e += (int64_t)nb * kRedThreads) {
+    const double we = w[e];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (v0 + g < k) s[g] += V[(int64_t)(v0 + g) * ldv + e] * we;
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (v0 + g >= k) break;  // uniform over the block
+    const double t = block_sum(s[g], sm);
+    if (threadIdx.x == 0) partials[(int64_t)(v0 + g) * nb + blockIdx.x] = t;
+  }
+}
+
 // partials of sum_e x_e y_e / c2_e (the inner product in which c^2 Delta_h,
 // and hence the WaveHoltz operator, is self-adjoint)
 template <typename TC>
@@ -752,7 +778,10 @@ int reduction_blocks(int64_t n) {
 
 hipError_t launch_mdot(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *partials, int nb,
                        hipStream_t s) {
-  mdot_kernel<<<dim3((unsigned)nb, (unsigned)k), kRedThreads, 0, s>>>(V, ldv, w, n, partials, nb);
+  if (k == 1) mdot_kernel<<<dim3((unsigned)nb, 1u), kRedThreads, 0, s>>>(V, ldv, w, n, partials, nb);
+  else
+    mdot_group_kernel<kMdotGroup><<<dim3((unsigned)nb, (unsigned)((k + kMdotGroup - 1) / kMdotGroup)), kRedThreads, 0,
+                                    s>>>(V, ldv, k, w, n, partials, nb);
   return hipGetLastError();
 }
 
