@@ -795,7 +795,9 @@ def run_batch(args, dev):
     pts = sum(i["applies"] * pa for i, pa in zip(infos, pts_apply))
     value = pts / elapsed / 1e9
     its = [i["iters"] for i in infos]
-    helm = max(s.helmholtz_residual(x) for s, x in zip(solvers, xs))
+    helms = [s.helmholtz_residual(x) for s, x in zip(solvers, xs)]
+    helm = max(helms)
+    worst = int(np.argmax(helms))
     log(f"batched: {elapsed:.2f}s, {value:.1f} GPts/s, iterations {min(its)}..{max(its)}")
 
     seq = None
@@ -834,6 +836,11 @@ def run_batch(args, dev):
         "converged": all(i["converged"] for i in infos),
         "max_rel_res": max(i["rel_res"] for i in infos),
         "helmholtz_rel_res_max": helm,
+        # the Helmholtz residual weights an error mode by |omega^2 - lambda^2|
+        # where the WaveHoltz residual weights it by |1 - beta_d|; near
+        # resonance the ratio is large (the worst problem and why: design notes)
+        "helmholtz_worst_problem": {"n": probs[worst]["n"], "omega": probs[worst]["omega"],
+                                    "rel_res": infos[worst]["rel_res"], "helmholtz_rel_res": helms[worst]},
         "iters_min_median_max": [min(its), int(np.median(its)), max(its)],
         "sequential": seq,
         "speedup_vs_sequential": round(seq["time_to_residual_s"] / elapsed, 3) if seq else None,

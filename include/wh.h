@@ -584,6 +584,27 @@ WH_API wh_status wh_batch_apply(wh_batch *batch, const double *const *v, double 
  * per problem (rel_res is the true residual at exit).  Synchronises. */
 WH_API wh_status wh_batch_solve(wh_batch *batch, const wh_solve_opts *opts, double *const *x, wh_solve_info *info);
 
+/* As wh_batch_solve with given right-hand sides: (I - S_h) x_i = b[i] (device
+ * FP64 node arrays, one per problem, not aliasing x[i]; copied at the start).
+ * A problem whose b[i] is zero is left as it is (rel_res 0). */
+WH_API wh_status wh_batch_solve_rhs(wh_batch *batch, const wh_solve_opts *opts, const double *const *b,
+                                   double *const *x, wh_solve_info *info);
+
+/* Residual correction over two finalized batches of the same problems in the
+ * same order: `hi` of WH_FP64 contexts, `lo` of WH_FP32_STATE contexts (same
+ * grids, orders and time parameters).  Each outer iteration forms every
+ * problem's FP64 residual r_i = b_i - A x_i on hi (b_i = W_h(0, f_i) in FP64,
+ * once), solves A d_i = r_i approximately by the batched CG on lo (`inner`:
+ * CG, its rtol and maxit; problems already at outer->rtol get d_i = 0) and
+ * sets x_i += d_i, until every problem has ||r_i|| <= outer->rtol ||b_i|| or
+ * outer->maxit corrections were made.  The filter accumulation, the Krylov
+ * vectors and the residuals stay FP64; lo's state and stencil are FP32.
+ * info[i]: iters = corrections of problem i, applies counts both precisions,
+ * rel_res = its FP64 residual.  Returns WH_ENOTCONV if a problem did not
+ * reach outer->rtol; WH_EINVAL for mismatched batches or precisions. */
+WH_API wh_status wh_batch_solve_mixed(wh_batch *hi, wh_batch *lo, const wh_solve_opts *outer,
+                                     const wh_solve_opts *inner, double *const *x, wh_solve_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2793,7 +2793,10 @@ wh_status wh_batch_apply(wh_batch *b, const double *const *v, double *const *out
   return batch_enqueue_apply(b, with_forcing != 0, wh::FINAL_FILTER, b->stream);
 }
 
-wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, wh_solve_info *info) {
+// The batched CG; rhs (nullable) gives every problem's right-hand side
+// (device FP64 node arrays) instead of b_i = W_h(0, f_i).
+static wh_status batch_solve_core(wh_batch *b, const wh_solve_opts *o, double *const *x, wh_solve_info *info,
+                                  const double *const *rhs) {
   WH_TRY(batch_need(b));
   if (!o || !x) return bfail(b, WH_EINVAL, "opts or x is NULL");
   if (o->method != WH_SOLVER_CG) return bfail(b, WH_EINVAL, "batches are solved with WH_SOLVER_CG");
@@ -2802,8 +2805,11 @@ wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, 
     return bfail(b, WH_EINVAL, "maxit must be >= 1 and rtol finite and > 0");
   WH_BHIP(b, hipSetDevice(b->device));
   const size_t P = b->probs.size();
-  for (size_t i = 0; i < P; ++i)
+  for (size_t i = 0; i < P; ++i) {
     if (!x[i] || !is_device_ptr(x[i])) return bfail(b, WH_EINVAL, "x[%zu] is not device memory", i);
+    if (rhs && (!rhs[i] || !is_device_ptr(rhs[i]))) return bfail(b, WH_EINVAL, "b[%zu] is not device memory", i);
+    if (rhs && rhs[i] == x[i]) return bfail(b, WH_EINVAL, "b[%zu] may not alias x[%zu]", i, i);
+  }
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = b->own;
   // order after the caller's stream and the problems' own uploads
@@ -2829,10 +2835,17 @@ wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, 
   for (size_t i = 0; i < P; ++i) all[i] = (int)i;
   const bool fp32 = b->prec == WH_FP32_STATE;
 
-  // b_i = W_h(0, f_i) and ||b_i||: r = b - 0, then <r,r>
-  WH_TRY(batch_select(b, all, zero.data(), bout.data(), true, x, nullptr, s));
-  WH_TRY(batch_enqueue_apply(b, true, wh::FINAL_FILTER, s));
-  for (auto &a : applies) ++a;
+  // b_i = W_h(0, f_i) (or the given right-hand side) and ||b_i||: r = b - 0,
+  // then <r,r>
+  if (rhs) {
+    WH_TRY(batch_select(b, all, zero.data(), bout.data(), false, x, nullptr, s));
+    for (size_t i = 0; i < P; ++i)
+      WH_BHIP(b, hipMemcpyAsync(bout[i], rhs[i], (size_t)b->probs[i]->nodes * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    WH_TRY(batch_select(b, all, zero.data(), bout.data(), true, x, nullptr, s));
+    WH_TRY(batch_enqueue_apply(b, true, wh::FINAL_FILTER, s));
+    for (auto &a : applies) ++a;
+  }
   {
     // Euclidean table with q = 0
     std::vector<wh::BatchVec> ve = b->vecs;
@@ -2945,6 +2958,147 @@ wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, 
   }
   if (st == WH_OK && unconverged)
     st = bfail(b, WH_ENOTCONV, "%d problems did not reach rtol within maxit = %d", unconverged, o->maxit);
+  return st;
+}
+
+wh_status wh_batch_solve(wh_batch *b, const wh_solve_opts *o, double *const *x, wh_solve_info *info) {
+  return batch_solve_core(b, o, x, info, nullptr);
+}
+
+wh_status wh_batch_solve_rhs(wh_batch *b, const wh_solve_opts *o, const double *const *rhs, double *const *x,
+                             wh_solve_info *info) {
+  if (b && !rhs) return bfail(b, WH_EINVAL, "b is NULL");
+  return batch_solve_core(b, o, x, info, rhs);
+}
+
+// Residual correction over two batches of the same problems: FP64 residuals
+// r_i = b_i - A x_i on `hi`, corrections A d_i = r_i by the batched CG on the
+// FP32-state batch `lo` (converged problems get d_i = 0), x_i += d_i.
+wh_status wh_batch_solve_mixed(wh_batch *hi, wh_batch *lo, const wh_solve_opts *outer, const wh_solve_opts *inner,
+                               double *const *x, wh_solve_info *info) {
+  WH_TRY(batch_need(hi));
+  if (!lo) return bfail(hi, WH_EINVAL, "lo is NULL");
+  if (!lo->finalized) return bfail(hi, WH_ESTATE, "the FP32-state batch is not finalized");
+  if (!outer || !inner || !x) return bfail(hi, WH_EINVAL, "opts or x is NULL");
+  if (outer->maxit < 1 || !(outer->rtol > 0.0) || !std::isfinite(outer->rtol))
+    return bfail(hi, WH_EINVAL, "outer maxit must be >= 1 and outer rtol finite and > 0");
+  if (hi->prec != WH_FP64 || lo->prec != WH_FP32_STATE)
+    return bfail(hi, WH_EINVAL, "hi must hold WH_FP64 contexts and lo WH_FP32_STATE contexts");
+  if (hi->device != lo->device) return bfail(hi, WH_EINVAL, "the batches are on different devices");
+  const size_t P = hi->probs.size();
+  if (lo->probs.size() != P) return bfail(hi, WH_EINVAL, "the batches hold different numbers of problems");
+  for (size_t i = 0; i < P; ++i) {
+    const wh_ctx *a = hi->probs[i], *c = lo->probs[i];
+    if (a->dim != c->dim || a->order != c->order || a->n[0] != c->n[0] || a->n[1] != c->n[1] ||
+        a->tp.nt != c->tp.nt || a->tp.periods != c->tp.periods || a->tp.dt != c->tp.dt || a->tp.alpha != c->tp.alpha)
+      return bfail(hi, WH_EINVAL, "problem %zu: the two contexts differ in grid, order or time parameters", i);
+    if (!x[i] || !is_device_ptr(x[i])) return bfail(hi, WH_EINVAL, "x[%zu] is not device memory", i);
+  }
+  WH_BHIP(hi, hipSetDevice(hi->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = hi->own;
+  for (wh_ctx *c : hi->probs) WH_BHIP(hi, hipStreamSynchronize(c->stream));
+  for (wh_ctx *c : lo->probs) WH_BHIP(hi, hipStreamSynchronize(c->stream));
+  WH_BHIP(hi, hipEventRecord(hi->ev, hi->stream));
+  WH_BHIP(hi, hipStreamWaitEvent(s, hi->ev, 0));
+
+  std::vector<const double *> zero(P), xin(P), rhs(P);
+  std::vector<double *> bout(P), qout(P), d(P);
+  for (size_t i = 0; i < P; ++i) {
+    wh_ctx *c = hi->probs[i];
+    WH_BHIP(hi, wh::launch_fill(c->tmp, 0.0, c->nodes, s));
+    zero[i] = c->tmp;
+    bout[i] = c->b;
+    xin[i] = x[i];
+    qout[i] = c->V + 2 * c->ldv;
+    d[i] = c->tmp;                            // the correction
+    rhs[i] = c->V;                            // r_i of the last residual
+  }
+  std::vector<double> sc(P * kBatchStride, 0.0), bnorm(P, 0.0), rel(P, 1.0);
+  std::vector<int> corr(P, 0), applies(P, 0);
+  std::vector<int> all(P);
+  for (size_t i = 0; i < P; ++i) all[i] = (int)i;
+
+  // b_i = W_h(0, f_i) in FP64 and ||b_i||
+  WH_TRY(batch_select(hi, all, zero.data(), bout.data(), true, x, nullptr, s));
+  WH_TRY(batch_enqueue_apply(hi, true, wh::FINAL_FILTER, s));
+  for (auto &a : applies) ++a;
+  {
+    std::vector<wh::BatchVec> ve = hi->vecs;
+    for (size_t t = 0; t < P; ++t) {
+      ve[t].c2 = nullptr;
+      ve[t].q = hi->probs[(size_t)hi->ids[t]]->tmp;
+    }
+    WH_BHIP(hi, hipMemcpyAsync(hi->d_vecs_e, ve.data(), P * sizeof(wh::BatchVec), hipMemcpyHostToDevice, s));
+    WH_BHIP(hi, wh::launch_batch_residual(hi->d_vecs_e, (int)P, hi->red_blocks, s));
+    WH_BHIP(hi, wh::launch_batch_dot(false, hi->d_vecs_e, (int)P, hi->red_blocks, 1, hi->d_part, hi->d_sc + 1,
+                                     kBatchStride, s));
+    WH_TRY(batch_fetch(hi, sc.data(), s));
+  }
+  for (size_t i = 0; i < P; ++i) {
+    bnorm[i] = std::sqrt(sc[i * kBatchStride + 1]);
+    if (!std::isfinite(bnorm[i])) return bfail(hi, WH_ENONFINITE, "problem %zu: ||b|| is not finite", i);
+  }
+  wh_status st = WH_OK;
+  std::vector<wh_solve_info> in(P);
+  for (int k = 0;; ++k) {
+    // FP64 residual r_i = b_i - A x_i (into the r vector of hi's problems)
+    WH_TRY(batch_select(hi, all, xin.data(), qout.data(), false, x, nullptr, s));
+    WH_TRY(batch_enqueue_apply(hi, false, wh::FINAL_A, s));
+    WH_BHIP(hi, wh::launch_batch_residual(hi->d_vecs, (int)P, hi->red_blocks, s));
+    WH_BHIP(hi, wh::launch_batch_dot(false, hi->d_vecs_e, (int)P, hi->red_blocks, 1, hi->d_part, hi->d_sc + 1,
+                                     kBatchStride, s));
+    WH_TRY(batch_fetch(hi, sc.data(), s));
+    bool all_done = true;
+    double worst = 0.0;
+    for (size_t i = 0; i < P; ++i) {
+      ++applies[i];
+      rel[i] = bnorm[i] > 0.0 ? std::sqrt(sc[i * kBatchStride + 1]) / bnorm[i] : 0.0;
+      if (!std::isfinite(rel[i])) return bfail(hi, WH_ENONFINITE, "problem %zu: residual is not finite", i);
+      all_done = all_done && rel[i] <= outer->rtol;
+      worst = std::max(worst, rel[i]);
+    }
+    if (outer->on_iter) outer->on_iter(k, worst, outer->user);
+    if (all_done || k >= outer->maxit) break;
+    // corrections: problems already converged get a zero right-hand side
+    for (size_t i = 0; i < P; ++i) {
+      WH_BHIP(hi, wh::launch_fill(d[i], 0.0, hi->probs[i]->nodes, s));
+      if (rel[i] <= outer->rtol) WH_BHIP(hi, wh::launch_fill(hi->probs[i]->V, 0.0, hi->probs[i]->nodes, s));
+    }
+    WH_BHIP(hi, hipStreamSynchronize(s));
+    const wh_status sl = batch_solve_core(lo, inner, d.data(), in.data(), rhs.data());
+    if (sl != WH_OK && sl != WH_ENOTCONV) {
+      st = bfail(hi, sl, "inner batched solve failed: %s", lo->err.c_str());
+      break;
+    }
+    for (size_t i = 0; i < P; ++i) {
+      applies[i] += in[i].applies;
+      if (rel[i] > outer->rtol) ++corr[i];
+      WH_BHIP(hi, wh::launch_add(x[i], d[i], x[i], hi->probs[i]->nodes, s));
+    }
+  }
+  WH_BHIP(hi, hipStreamSynchronize(s));
+  batch_drop_graphs(hi);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int unconverged = 0;
+  for (size_t i = 0; i < P; ++i) {
+    unconverged += rel[i] > outer->rtol;
+    if (!info) continue;
+    wh_ctx *c = hi->probs[i];
+    wh_solve_info &o = info[i];
+    std::memset(&o, 0, sizeof o);
+    o.iters = corr[i];
+    o.applies = applies[i];
+    o.rel_res = rel[i];
+    o.bnorm = bnorm[i];
+    o.scaled_res = rel[i] * bnorm[i] / std::sqrt((double)c->nodes);
+    o.cr_last = o.cr_avg = o.ecr = o.mu_pred = NAN;
+    o.rel_res_recursive = o.ritz_min = o.ritz_max = NAN;
+    o.seconds = secs;
+    o.point_steps = applies[i] * point_steps_per_apply(c);
+  }
+  if (st == WH_OK && unconverged)
+    st = bfail(hi, WH_ENOTCONV, "%d problems did not reach rtol within %d corrections", unconverged, outer->maxit);
   return st;
 }
 

@@ -149,6 +149,10 @@ def _load():
         "wh_batch_apply": (st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32]),
         "wh_batch_solve": (st, [_vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(_vp),
                                 ctypes.POINTER(wh_solve_info)]),
+        "wh_batch_solve_rhs": (st, [_vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(wh_solve_info)]),
+        "wh_batch_solve_mixed": (st, [_vp, _vp, ctypes.POINTER(wh_solve_opts), ctypes.POINTER(wh_solve_opts),
+                                      ctypes.POINTER(_vp), ctypes.POINTER(wh_solve_info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -520,6 +524,24 @@ def wh_batch_solve(batch, opts: wh_solve_opts, x: list) -> tuple[int, list]:
     return st, [infos[i] for i in range(len(x))]
 
 
+def wh_batch_solve_rhs(batch, opts: wh_solve_opts, b: list, x: list) -> tuple[int, list]:
+    """Batched CG with given right-hand sides; (status, infos)."""
+    infos = (wh_solve_info * max(len(x), 1))()
+    st = _load().wh_batch_solve_rhs(batch, ctypes.byref(opts), _ptrs(b), _ptrs(x), infos)
+    if st not in (WH_OK, WH_ENOTCONV):
+        _bcheck(batch, st)
+    return st, [infos[i] for i in range(len(x))]
+
+
+def wh_batch_solve_mixed(hi, lo, outer: wh_solve_opts, inner: wh_solve_opts, x: list) -> tuple[int, list]:
+    """Batched residual correction (FP64 hi, FP32-state lo); (status, infos)."""
+    infos = (wh_solve_info * max(len(x), 1))()
+    st = _load().wh_batch_solve_mixed(hi, lo, ctypes.byref(outer), ctypes.byref(inner), _ptrs(x), infos)
+    if st not in (WH_OK, WH_ENOTCONV):
+        _bcheck(hi, st)
+    return st, [infos[i] for i in range(len(x))]
+
+
 # --------------------------------------------------------------------------
 # convenience objects over torch tensors
 # --------------------------------------------------------------------------
@@ -815,11 +837,32 @@ class Batch:
                        [s._dev(o, "out") for s, o in zip(self.solvers, outs)], with_forcing)
         return outs
 
-    def solve(self, rtol=1e-8, maxit=1000, x0=None, callback=None):
-        """CG on every problem; returns (list of x, list of info dicts)."""
+    def solve(self, rtol=1e-8, maxit=1000, x0=None, callback=None, b=None):
+        """CG on every problem (right-hand sides W_h(0, f_i), or the device
+        tensors b); returns (list of x, list of info dicts)."""
         xs = [s.new() for s in self.solvers] if x0 is None else [x.clone() for x in x0]
         opts, cb = make_opts("cg", rtol, maxit, 2, callback)
-        st, infos = wh_batch_solve(self.batch, opts, [s._dev(x, "x") for s, x in zip(self.solvers, xs)])
+        xp = [s._dev(x, "x") for s, x in zip(self.solvers, xs)]
+        if b is None:
+            st, infos = wh_batch_solve(self.batch, opts, xp)
+        else:
+            st, infos = wh_batch_solve_rhs(self.batch, opts, [s._dev(bb, "b") for s, bb in zip(self.solvers, b)], xp)
+        out = []
+        for inf in infos:
+            d = inf.as_dict()
+            d["converged"] = d["rel_res"] <= rtol
+            out.append(d)
+        return xs, out
+
+    def solve_mixed(self, lo, rtol=1e-8, maxit=50, inner_rtol=1e-3, inner_maxit=5000, x0=None, callback=None):
+        """Residual correction: FP64 residuals on this batch (FP64 solvers),
+        corrections by the batched CG on `lo`, a Batch of the same problems
+        with FP32 state; returns (list of x, list of info dicts)."""
+        xs = [s.new() for s in self.solvers] if x0 is None else [x.clone() for x in x0]
+        outer, cb = make_opts("cg", rtol, maxit, 2, callback)
+        inner, _ = make_opts("cg", inner_rtol, inner_maxit, 2)
+        st, infos = wh_batch_solve_mixed(self.batch, lo.batch, outer, inner,
+                                         [s._dev(x, "x") for s, x in zip(self.solvers, xs)])
         out = []
         for inf in infos:
             d = inf.as_dict()

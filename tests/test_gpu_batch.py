@@ -104,6 +104,57 @@ def test_batch_apply(torch, prec, order, forcing):
         assert _err(prec, got, single, p.v) <= (1e-14 if prec == "fp64" else 1e-6), p.grid.n
 
 
+def test_batch_full_size_members_sampled(torch):
+    """Batch members at the batched configuration's full sizes (256^2, 512^2
+    and 1024^2, c = 1, 2nd order, Gaussian sources drawn as in the batched
+    workload) together with the small mixed problems, the default tuning:
+    W_h(v, f) of every full-size member at sampled nodes (corners, edges,
+    the source peak, inner nodes) against the oracle on the domain of
+    dependence, relative L2 over the samples <= 1e-11, and the
+    single-problem path's result within 1e-14."""
+    from paper_2504_03074_amd import Batch, Solver
+    _say("[batch full-size members] 256^2, 512^2, 1024^2")
+    draws = wl.batched_problems(64)
+    picks = []
+    for size in (256, 512, 1024):
+        picks.append(next(p for p in draws if p["n"] == size))
+    small = _mix(2, seed0=700)
+    solvers, members = [], []
+    for i, p in enumerate(picks):
+        n = p["n"]
+        grid = oc.Grid(2, (n, n), 2)
+        f = wl.materialise_source(2, n, p["source"])
+        v = wl.random_field(grid.shape, seed=900 + i)
+        s = Solver(2, (n, n), order=2, precision="fp64", restart=2)
+        s.set_c2(1.0)
+        s.set_source(f)
+        s.set_frequency(p["omega"], periods=p["periods"], cfl_frac=p["cfl"])
+        solvers.append(s)
+        members.append((grid, f, v, p))
+    solvers += [q.solver("fp64", 2) for q in small]
+    batch = Batch(solvers)
+    vs = [_to_dev(torch, m[2]) for m in members] + [_to_dev(torch, q.v) for q in small]
+    outs = batch.apply(vs, with_forcing=True)
+    torch.cuda.synchronize()
+    for (grid, f, v, p), s, vd, o in zip(members, solvers, vs, outs):
+        n = grid.n[0]
+        tp = oc.time_params(grid, 1.0, p["omega"], periods=p["periods"], cfl_frac=p["cfl"])
+        assert s.time_params["nt"] == tp["nt"]
+        peak = np.unravel_index(int(np.argmax(np.abs(f))), f.shape)
+        pts = [(1, 1), (n - 1, n - 1), (2, n // 2), (n // 2, n - 3), (int(peak[1]), int(peak[0])),
+               (n // 3, n // 4), (3 * n // 4, 2 * n // 3)]
+        want = oc.apply_at_points(grid, 1.0, f, v, tp, pts, with_forcing=True)
+        got = o.cpu().numpy()
+        g = np.array([got[q[1], q[0]] for q in pts])
+        err = _rel(g, want)
+        _say(f"    {n}^2 omega {p['omega']:.1f} nt {tp['nt']}: rel L2 over {len(pts)} samples {err:.2e}")
+        assert err <= TOL["fp64"]
+        assert _rel(got, s.apply(vd, with_forcing=True).cpu().numpy()) <= 1e-14
+    for q, o in zip(small, outs[len(members):]):
+        want = oc.apply(q.grid, q.c2, q.f, q.v, q.tp, with_forcing=True)
+        assert _rel(o.cpu().numpy(), want) <= TOL["fp64"], q.grid.n
+
+
 @pytest.mark.parametrize("order,kblock,tile", [(4, 2, 40), (4, 3, 80), (4, 4, 40), (4, 6, 80), (2, 4, 32),
                                                (2, 8, 64)])
 def test_batch_apply_tunings(torch, order, kblock, tile):
@@ -172,6 +223,56 @@ def test_batch_cg_fixed_iterations(torch, prec, iters):
             assert inf["rel_res"] == pytest.approx(true_rel, rel=1e-8)
         else:
             assert abs(inf["rel_res"] - true_rel) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("iters", [1, 7])
+def test_batch_cg_with_given_rhs_fixed_iterations(torch, iters):
+    """Batched CG on (I - S_h) x_i = b_i with given right-hand sides
+    (wh_batch_solve_rhs), k iterations against k oracle CG iterations on the
+    same b_i; a zero right-hand side leaves its problem at x = 0."""
+    from paper_2504_03074_amd import Batch
+    _say(f"[batch cg rhs] iters={iters}")
+    probs = _mix(2, seed0=800)
+    batch = Batch([p.solver("fp64", 2) for p in probs])
+    bs = [wl.random_field(p.grid.shape, seed=810 + i) for i, p in enumerate(probs)]
+    bs[1] = np.zeros(probs[1].grid.shape)
+    xs, infos = batch.solve(rtol=1e-300, maxit=iters, b=[_to_dev(torch, b) for b in bs])
+    for i, (p, x, inf, b) in enumerate(zip(probs, xs, infos, bs)):
+        got = x.cpu().numpy()
+        if i == 1:
+            assert not got.any() and inf["rel_res"] == 0.0
+            continue
+        want, _ = oc.cg(p.grid, p.c2, p.f, p.tp, fixed_iters=iters, b=b)
+        assert inf["iters"] == iters
+        assert _rel(got, want) <= TOL["fp64"], p.grid.n
+
+
+def test_batch_mixed_precision_refinement(torch):
+    """Batched residual correction (wh_batch_solve_mixed): FP64 residuals of
+    every problem, corrections by the batched FP32-state CG, reaching each
+    problem's FP64 discrete Helmholtz solution (sparse direct solve) while
+    the plain FP32-state batched solve does not."""
+    from paper_2504_03074_amd import Batch
+    _say("[batch mixed]")
+    probs = []
+    for i, (n, om_range) in enumerate([((40, 31), (5.0, 15.0)), ((33, 45), (6.0, 14.0)), ((52, 27), (4.0, 12.0))]):
+        p = Prob(n, "var", 0.0, 1, 4, seed=850 + 10 * i)
+        p.omega = _best_omega(p.grid, p.c2, np.linspace(*om_range, 17))
+        p.tp = oc.time_params(p.grid, p.c2, p.omega)
+        probs.append(p)
+    hi = Batch([p.solver("fp64", 4) for p in probs])
+    lo = Batch([p.solver("fp32", 4) for p in probs])
+    xs, infos = hi.solve_mixed(lo, rtol=1e-11, maxit=40, inner_rtol=1e-4, inner_maxit=5000)
+    x32, _ = lo.solve(rtol=1e-6, maxit=5000)
+    for p, x, inf, y in zip(probs, xs, infos, x32):
+        assert inf["converged"], inf
+        U = cf.dhs_direct(p.grid, p.c2, p.f, p.omega)
+        err = _rel(x.cpu().numpy(), U)
+        err32 = _rel(y.cpu().numpy(), U)
+        _say(f"    {p.grid.n} omega {p.omega:.2f}: {inf['iters']} corrections, mixed error {err:.2e}, "
+             f"FP32-state solve error {err32:.2e}")
+        assert err <= 1e-9
+        assert err32 > 10 * err
 
 
 def _best_omega(grid, c2, candidates):
