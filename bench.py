@@ -406,6 +406,47 @@ def cpu_baseline_grid(dim, n, order, c2, omega, steps, threads=None):
     return grid.unknowns * tp["nt"] / sec / 1e9, used, sec
 
 
+def run_c1(dev, reps=5):
+    """The 128^2 single-Gaussian configuration end to end on the GPU: 30
+    fixed-point iterations from v = 0 (FP64, 2nd order, c = 1, omega = 10.3),
+    the best of `reps` timed runs after one untimed; returns the record and
+    the workload (for the CPU oracle's run of the same iterations)."""
+    import torch
+    import workloads as wl
+    from paper_2504_03074_amd import Solver
+    w = wl.single_gaussian_source()
+    s = Solver(2, (w["n"], w["n"]), order=2, precision="fp64", restart=2)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    tp = s.set_frequency(w["omega"])
+    s.solve(method="fpi", rtol=0.0, maxit=w["fpi_iters"])
+    best, info = None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(method="fpi", rtol=0.0, maxit=w["fpi_iters"])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        best = t if best is None else min(best, t)
+    pts = (w["n"] - 1) ** 2 * tp["nt"] * info["applies"]
+    return {"workload": "square 128^2, order 2, c = 1, omega = 10.3, Gaussian exp(-200|x-(0.4,0.6)|^2), "
+                        "30 fixed-point iterations, FP64",
+            "seconds": round(best, 5), "applies": info["applies"], "nt": tp["nt"],
+            "GPts_per_s": round(pts / best * 1e-9, 3), "cr_last": info["cr_last"],
+            "mu_pred": info["mu_pred"]}, w
+
+
+def cpu_c1(w):
+    """The FP64 CPU oracle's 30 fixed-point iterations of the 128^2
+    configuration, end to end."""
+    from oracle import core as oc
+    grid = oc.Grid(2, (w["n"], w["n"]), 2)
+    tp = oc.time_params(grid, w["c2"], w["omega"])
+    t0 = time.perf_counter()
+    oc.fpi(grid, w["c2"], w["f"], tp, w["fpi_iters"])
+    return time.perf_counter() - t0
+
+
 def run_square_reference(dev, log_every=0):
     """One FP64 CG solve of the 2048^2 configuration to the residual target
     (after one untimed application): time to residual and rate."""
@@ -539,6 +580,9 @@ def run_cube_block(args, dev):
     if args.square:
         log("2048^2 FP64 CG solve to 1e-8 (time to residual)")
         result["square_fp64_time_to_residual"] = run_square_reference(dev)
+    log("128^2 single-Gaussian configuration: 30 fixed-point iterations")
+    c1, w1 = run_c1(dev)
+    result["c1_fpi_30_iterations"] = c1
     if args.cpu_baseline:
         steps = 24
         log(f"CPU oracle baseline: {steps} leapfrog steps of the {n}^3 grid on the host cores")
@@ -554,6 +598,9 @@ def run_cube_block(args, dev):
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
         }
+        sec_c1 = cpu_c1(w1)
+        result["cpu_baseline"]["c1_end_to_end_s"] = round(sec_c1, 3)
+        result["c1_fpi_30_iterations"]["cpu_oracle_s"] = round(sec_c1, 3)
     print(json.dumps(result), flush=True)
 
 
