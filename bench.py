@@ -580,6 +580,10 @@ def run_cube_block(args, dev):
             "launches": prof["launches"],
             "measured_copy_GBps": ceil["copy_GBps"],
             "frac_of_measured_copy": round(achieved / ceil["copy_GBps"], 4),
+            # the same 36-byte-per-node mix streamed elementwise (no stencil,
+            # no halo): the practical ceiling for this kernel's algorithmic bytes
+            "measured_pass_mix_GBps": ceil["pass_mix_GBps"],
+            "frac_of_measured_pass_mix": round(achieved / ceil["pass_mix_GBps"], 4),
             "stream_kernel_GBps": ceil,
             "kernel_GPts_per_s": round(prof["point_steps"] / prof["ms"] * 1e-6, 2),
             "unblocked_bytes_per_point_step": ub,
@@ -727,6 +731,15 @@ def stream_ceilings(dev, nbytes=1 << 30):
         ms = wh_stream_bandwidth(kind, a.data_ptr(), b.data_ptr(), nbytes, 0, 10, stream)
         out[f"{name}_GBps"] = round(moved / (ms * 1e-3) * 1e-9, 1)
     del a, b
+    # the FP32 blocked pass's per-node traffic (three FP32 arrays and the FP64
+    # accumulator read, two FP32 arrays and the accumulator written: 36 B) on
+    # 2^27 nodes, elementwise with 16-byte accesses: the ceiling for that mix
+    nodes = 1 << 27
+    src = torch.zeros(nodes * 3, dtype=torch.float32, device=dev)
+    dst = torch.zeros(nodes * 4, dtype=torch.float32, device=dev)
+    ms = wh_stream_bandwidth(3, src.data_ptr(), dst.data_ptr(), 36 * nodes, 0, 10, stream)
+    out["pass_mix_GBps"] = round(36 * nodes / (ms * 1e-3) * 1e-9, 1)
+    del src, dst
     torch.cuda.empty_cache()
     return out
 

@@ -393,6 +393,12 @@ WH_API wh_status wh_filter_spectrum(wh_ctx *ctx, double c2, double *a_min, doubl
  *   kind 0  copy src -> dst (buffers must not overlap; 2 x bytes moved)
  *   kind 1  read src (dst unused, may be NULL; bytes moved)
  *   kind 2  write dst (src unused, may be NULL; bytes moved)
+ *   kind 3  the per-node traffic of an FP32-state blocked pass without its
+ *           stencil, over nodes = bytes / 36 (bytes a multiple of 144): src
+ *           holds three FP32 arrays of `nodes` values (read: W^{n-1}, W^n,
+ *           c^2), dst two FP32 arrays (written) followed by one FP64 array
+ *           (read and written); src needs bytes / 3 and dst bytes * 4 / 9
+ *           bytes, not overlapping (bytes moved)
  * groups = work-groups of 256 lanes (0 = 1024, the fastest copy measured on
  * MI355X).  *ms_per_launch receives the average launch time.  Errors:
  * WH_EINVAL for a bad kind, size, alignment, group count, repetition count

@@ -1251,13 +1251,15 @@ wh_status wh_filter_spectrum(wh_ctx *c, double c2, double *a_min, double *a_max,
 
 wh_status wh_stream_bandwidth(int32_t kind, const void *src, void *dst, size_t bytes, int32_t groups, int32_t reps,
                               void *stream, double *ms_per_launch) {
-  if (kind < 0 || kind > 2 || !ms_per_launch || reps < 1 || reps > 10000) return WH_EINVAL;
-  if (bytes < 16 || bytes % 16 != 0 || bytes > ((size_t)1 << 40)) return WH_EINVAL;
+  if (kind < 0 || kind > 3 || !ms_per_launch || reps < 1 || reps > 10000) return WH_EINVAL;
+  if (bytes < 16 || bytes % (kind == 3 ? 144 : 16) != 0 || bytes > ((size_t)1 << 40)) return WH_EINVAL;
   if (groups < 0 || groups > 65535) return WH_EINVAL;
   if (kind != 2 && (!src || !is_device_ptr(src) || reinterpret_cast<uintptr_t>(src) % 16 != 0)) return WH_EINVAL;
   if (kind != 1 && (!dst || !is_device_ptr(dst) || reinterpret_cast<uintptr_t>(dst) % 16 != 0)) return WH_EINVAL;
-  if (kind == 0 && static_cast<const char *>(src) < static_cast<const char *>(dst) + bytes &&
-      static_cast<const char *>(dst) < static_cast<const char *>(src) + bytes)
+  // kind 3: src holds 12 B and dst 16 B per node (bytes / 36 nodes)
+  const size_t src_len = kind == 3 ? bytes / 3 : bytes, dst_len = kind == 3 ? bytes / 36 * 16 : bytes;
+  if ((kind == 0 || kind == 3) && static_cast<const char *>(src) < static_cast<const char *>(dst) + dst_len &&
+      static_cast<const char *>(dst) < static_cast<const char *>(src) + src_len)
     return WH_EINVAL;
   const int g = groups > 0 ? groups : 1024;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -46,7 +46,9 @@ constexpr size_t kStaticScratchBytes = (size_t)192 << 20;
 hipError_t static_scratch(int device, void **ptr);
 
 // Streaming-bandwidth reference kernel: kind 0 copy, 1 read, 2 write of
-// `bytes` (a multiple of 16) with `groups` work-groups of 256 lanes.
+// `bytes` (a multiple of 16), kind 3 the FP32 blocked pass's per-node mix
+// (`bytes` = 36 x nodes, a multiple of 144), with `groups` work-groups of
+// 256 lanes.
 hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, int groups, float *sink,
                          hipStream_t s);
 

@@ -682,6 +682,34 @@ __global__ __launch_bounds__(256) void stream_kernel(const stream_vec *__restric
   }
 }
 
+typedef double stream_d2 __attribute__((ext_vector_type(2)));
+
+// The per-node traffic of a blocked pass of FP32 state without its stencil:
+// W^{n-1}, W^n and c^2 (FP32) and the FP64 accumulator read, two FP32 levels
+// and the accumulator written (36 B per node), four nodes per lane with
+// 16-byte accesses, grid-stride.  The values written are a cheap function of
+// the values read, so nothing can be elided.
+__global__ __launch_bounds__(256) void stream_mix_kernel(const stream_vec *__restrict__ ip,
+                                                         const stream_vec *__restrict__ ic,
+                                                         const stream_vec *__restrict__ c2,
+                                                         stream_d2 *__restrict__ acc, stream_vec *__restrict__ op,
+                                                         stream_vec *__restrict__ oc, int64_t n4) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const stream_vec a = ic[i], b = ip[i], c = c2[i];
+    const stream_vec nx = (a + a - b) + c * a;
+    stream_d2 lo = acc[2 * i], hi = acc[2 * i + 1];
+    lo.x += 0.5 * (double)nx.x;
+    lo.y += 0.5 * (double)nx.y;
+    hi.x += 0.5 * (double)nx.z;
+    hi.y += 0.5 * (double)nx.w;
+    op[i] = a;
+    oc[i] = nx;
+    acc[2 * i] = lo;
+    acc[2 * i + 1] = hi;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_first_step(bool fp32, const StepGeom &half, const double *v, void *W0, void *W1, double *acc,
@@ -755,9 +783,17 @@ hipError_t launch_set_walls(bool fp32, const StepGeom &g, void *a, double value,
 
 hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, int groups, float *sink,
                          hipStream_t s) {
-  const int64_t n = bytes / 16;
   const stream_vec *a = static_cast<const stream_vec *>(src);
   stream_vec *b = static_cast<stream_vec *>(dst);
+  if (kind == 3) {
+    // four nodes per 16-byte FP32 vector: src = W^{n-1}, W^n, c^2; dst =
+    // the two FP32 outputs, then the FP64 accumulator
+    const int64_t n4 = bytes / 144;
+    stream_mix_kernel<<<groups, 256, 0, s>>>(a, a + n4, a + 2 * n4, reinterpret_cast<stream_d2 *>(b + 2 * n4), b,
+                                             b + n4, n4);
+    return hipGetLastError();
+  }
+  const int64_t n = bytes / 16;
   if (kind == 0) stream_kernel<0><<<groups, 256, 0, s>>>(a, b, n, sink);
   else if (kind == 1) stream_kernel<1><<<groups, 256, 0, s>>>(a, b, n, sink);
   else stream_kernel<2><<<groups, 256, 0, s>>>(a, b, n, sink);

@@ -338,7 +338,8 @@ def wh_dot(ctx, x: int, y: int) -> float:
 def wh_stream_bandwidth(kind: int, src: int, dst: int, nbytes: int, groups: int = 0, reps: int = 10,
                         stream: int = 0) -> float:
     """Average milliseconds per launch of the library's streaming kernel
-    (kind 0 copy, 1 read, 2 write) over `nbytes` of device memory."""
+    (kind 0 copy, 1 read, 2 write) over `nbytes` of device memory, or (kind
+    3) of the FP32 blocked pass's per-node traffic over nbytes / 36 nodes."""
     ms = ctypes.c_double()
     st = _load().wh_stream_bandwidth(int(kind), _vp(src) if src else None, _vp(dst) if dst else None,
                                      int(nbytes), int(groups), int(reps), _vp(stream) if stream else None,

@@ -135,3 +135,48 @@ def test_single_interior_node_grids(torch, dim, n, order, kernel, kblock):
     got = s.apply(torch.from_numpy(v).cuda(), with_forcing=True).cpu().numpy()
     want = oc.apply(grid, c2, f, v, tp, with_forcing=True)
     assert np.linalg.norm(got - want) <= 1e-11 * np.linalg.norm(want)
+
+
+def test_stream_bandwidth_reference_kernels(torch):
+    """The streaming-bandwidth reference (used only to read rooflines): each
+    kind moves what it says, and bad sizes, kinds and overlaps are rejected."""
+    from paper_2504_03074_amd import wh
+    _say("[abi] streaming reference kernels")
+    dev = torch.device("cuda:0")
+    nodes = 4096
+    g = torch.Generator(device="cpu").manual_seed(11)
+    a = torch.rand(nodes, generator=g, dtype=torch.float32).to(dev)
+    b = torch.empty_like(a)
+    ms = wh.wh_stream_bandwidth(0, a.data_ptr(), b.data_ptr(), nodes * 4, 0, 2)
+    torch.cuda.synchronize()
+    assert ms > 0 and torch.equal(a, b)
+    wh.wh_stream_bandwidth(2, 0, b.data_ptr(), nodes * 4, 0, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(b.view(-1, 4).cpu(), torch.tensor([[1.0, 2.0, 3.0, 4.0]]).expand(nodes // 4, 4))
+    wh.wh_stream_bandwidth(1, a.data_ptr(), 0, nodes * 4, 0, 1)
+    # kind 3: src = (W^{n-1}, W^n, c^2), dst = (out_prev, out_cur, FP64 acc)
+    src = torch.rand(3 * nodes, generator=g, dtype=torch.float32).to(dev)
+    acc0 = torch.rand(nodes, generator=g, dtype=torch.float64)
+    dst = torch.zeros(4 * nodes, dtype=torch.float32, device=dev)
+    dst.view(torch.float64)[nodes:] = acc0.to(dev)
+    reps = 3  # one untimed launch and three timed ones: the accumulator gains four increments
+    wh.wh_stream_bandwidth(3, src.data_ptr(), dst.data_ptr(), 36 * nodes, 0, reps)
+    torch.cuda.synchronize()
+    ip, ic, c2 = src.cpu().view(3, nodes)
+    out_cur = dst[nodes:2 * nodes].cpu()
+    assert torch.equal(dst[:nodes].cpu(), ic)
+    # (2 W^n - W^{n-1}) + c^2 W^n in FP32 (the device may fuse the last multiply-add)
+    assert torch.allclose(out_cur, (ic + ic - ip) + c2 * ic, rtol=1e-6, atol=1e-6)
+    want = acc0.clone()
+    for _ in range(reps + 1):
+        want += 0.5 * out_cur.double()
+    assert torch.allclose(dst.view(torch.float64)[nodes:].cpu(), want, rtol=0, atol=1e-12)
+    # rejected: unknown kind, a size that is not whole vectors (or 144-byte
+    # groups for kind 3), overlapping buffers, too many repetitions
+    for args in ((4, a.data_ptr(), b.data_ptr(), nodes * 4, 0, 1),
+                 (0, a.data_ptr(), b.data_ptr(), 8, 0, 1),
+                 (3, src.data_ptr(), dst.data_ptr(), 36 * nodes + 36, 0, 1),
+                 (3, src.data_ptr(), src.data_ptr() + 512, 36 * 64, 0, 1),
+                 (0, a.data_ptr(), a.data_ptr() + 64, 1024, 0, 1),
+                 (0, a.data_ptr(), b.data_ptr(), nodes * 4, 0, 10001)):
+        assert _status(wh.wh_stream_bandwidth, *args) == wh.WH_EINVAL, args
