@@ -84,6 +84,16 @@ __device__ __forceinline__ void st_at(U *__restrict__ p, uint32_t e, U x) {
 #endif
 constexpr bool kSkipHaloWaves = WH_BLOCK_SKIP_HALO_WAVES != 0;
 
+// The FP64 4th-order kernel with variable c^2 keeps the forcing values of its
+// tile in LDS (NW*RS x 64 values) instead of registers: with them in
+// registers it needs 143 VGPRs, which leaves room for three waves per SIMD
+// and so one 8-wave group per CU instead of two.  Each lane reads back only
+// what it wrote, so no barrier is needed.
+template <typename T, int P, bool FORCE, bool CVAR>
+constexpr bool forcing_in_lds() {
+  return FORCE && CVAR && sizeof(T) == 8 && P == 4;
+}
+
 // XCD-aware tile order: consecutive work-groups are dispatched round-robin
 // over the 8 XCDs; give each XCD a contiguous run of tiles so that the halo
 // re-reads of neighbouring tiles hit the same L2.
@@ -99,7 +109,8 @@ __device__ __forceinline__ void advance_tile_impl(
     const StepGeom &g, int ksteps, int tx, int ty, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
     T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
     const T *__restrict__ fg, const BlockCoef &coef, int mode, const double *__restrict__ v,
-    double *__restrict__ out, T (*__restrict__ halo)[NW][2][P / 2][64]) {
+    double *__restrict__ out, T (*__restrict__ halo)[NW][2][P / 2][64], T (*__restrict__ fsh)[64]) {
+  constexpr bool FL = forcing_in_lds<T, P, FORCE, CVAR>();
   constexpr int R = P / 2;
   constexpr int H = K * R;
   constexpr int OX = 64 - 2 * H;
@@ -115,7 +126,7 @@ __device__ __forceinline__ void advance_tile_impl(
   const int gx = x0 - H + lane;
   const int gy0 = y0 - H + wave * RS;
 
-  T A[RS], B[RS], C2[RS], F[RS];
+  T A[RS], B[RS], C2[RS], F[FL ? 1 : RS];
   double ACC[RS];
   uint32_t own = 0;  // bit q: row q of this lane is an owned interior node
 
@@ -131,7 +142,8 @@ __device__ __forceinline__ void advance_tile_impl(
       B[q] = ld_at(in_prev, e);
       A[q] = ld_at(in_cur, e);
       C2[q] = CVAR ? ld_at(c2g, e) : static_cast<T>(g.c2const);
-      F[q] = FORCE ? ld_at(fg, e) : T(0);
+      if constexpr (FL) fsh[wave * RS + q][lane] = ld_at(fg, e);
+      else F[q] = FORCE ? ld_at(fg, e) : T(0);
       const int r = wave * RS + q;
       ACC[q] = 0.0;
       if (r >= H && r < H + OY) {
@@ -156,7 +168,8 @@ __device__ __forceinline__ void advance_tile_impl(
       B[q] = sg * in_prev[id];
       A[q] = sg * in_cur[id];
       C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
-      F[q] = FORCE ? sg * fg[id] : T(0);
+      if constexpr (FL) fsh[wave * RS + q][lane] = sg * fg[id];
+      else F[q] = FORCE ? sg * fg[id] : T(0);
       const int r = wave * RS + q;
       const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
       const bool wall = col_wall || iy == 0 || iy == g.ny;
@@ -231,7 +244,8 @@ __device__ __forceinline__ void advance_tile_impl(
           S = X + ry * Y;
         }
         T nxt = (T(2) - rc * CB[q]) * c - prv[q] + CB[q] * S;
-        if (FORCE) nxt += gn * F[q];
+        if constexpr (FL) nxt += gn * fsh[wave * RS + q][lane];
+        else if (FORCE) nxt += gn * F[q];
         prv[q] = nxt;
         ACC[q] += wn * static_cast<double>(nxt);
       }
@@ -275,7 +289,7 @@ __device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, int 
                                              double *__restrict__ acc, const T *__restrict__ c2g,
                                              const T *__restrict__ fg, const BlockCoef &coef, int mode,
                                              const double *__restrict__ v, double *__restrict__ out,
-                                             T (*__restrict__ halo)[NW][2][P / 2][64]) {
+                                             T (*__restrict__ halo)[NW][2][P / 2][64], T (*__restrict__ fsh)[64]) {
   constexpr int H = K * (P / 2);
   constexpr int OX = 64 - 2 * H;
   constexpr int OY = NW * RS - 2 * H;
@@ -285,10 +299,10 @@ __device__ __forceinline__ void advance_tile(const StepGeom &g, int ksteps, int 
                      g.nodes <= (int64_t(1) << 28);
   if (inner)
     advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, true>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur, acc,
-                                                          c2g, fg, coef, mode, v, out, halo);
+                                                          c2g, fg, coef, mode, v, out, halo, fsh);
   else
     advance_tile_impl<T, P, K, RS, NW, FORCE, CVAR, false>(g, ksteps, tx, ty, in_prev, in_cur, out_prev, out_cur,
-                                                           acc, c2g, fg, coef, mode, v, out, halo);
+                                                           acc, c2g, fg, coef, mode, v, out, halo, fsh);
 }
 
 template <typename T, int P, int K, int RS, int NW, bool FORCE, bool CVAR>
@@ -298,10 +312,11 @@ __global__ __launch_bounds__(64 * NW) void block_steps_kernel(
     const T *__restrict__ c2g, const T *__restrict__ fg, BlockCoef coef, int mode, const double *__restrict__ v,
     double *__restrict__ out) {
   __shared__ T halo[2][NW][2][P / 2][64];  // y-halo rows, double-buffered over steps
+  __shared__ T fsh[forcing_in_lds<T, P, FORCE, CVAR>() ? NW * RS : 1][64];
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= tiles_total) return;
   advance_tile<T, P, K, RS, NW, FORCE, CVAR>(g, ksteps, tile % tiles_x, tile / tiles_x, in_prev, in_cur, out_prev,
-                                             out_cur, acc, c2g, fg, coef, mode, v, out, halo);
+                                             out_cur, acc, c2g, fg, coef, mode, v, out, halo, fsh);
 }
 
 // Batched pass: work-group -> (problem, tile) through the prefix sums of the
@@ -313,6 +328,7 @@ __global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchD
                                                                     int pass, const BlockCoef *__restrict__ coefs,
                                                                     int final_mode) {
   __shared__ T halo[2][NW][2][P / 2][64];
+  __shared__ T fsh[forcing_in_lds<T, P, FORCE, true>() ? NW * RS : 1][64];
   const int total = tile_prefix[nactive];
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= total) return;
@@ -335,10 +351,10 @@ __global__ __launch_bounds__(64 * NW) void batch_block_steps_kernel(const BatchD
   const int tx = local % d.tiles_x, ty = local / d.tiles_x;
   if (d.c2)
     advance_tile<T, P, K, RS, NW, FORCE, true>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, static_cast<const T *>(d.c2),
-                                               static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
+                                               static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo, fsh);
   else
     advance_tile<T, P, K, RS, NW, FORCE, false>(d.g, ks, tx, ty, ip, ic, op, oc, d.acc, nullptr,
-                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo);
+                                                static_cast<const T *>(d.f), coef, mode, d.v, d.out, halo, fsh);
 }
 
 template <typename T, int P, int K, int RS, int NW>
