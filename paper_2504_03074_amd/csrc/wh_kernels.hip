@@ -149,6 +149,76 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
   first_step_node<T, DIM, P>(g, i, j, k, v, W0, W1, acc, c2, f, g0, w0, w1);
 }
 
+// 3-D first step with z coarsening: thread (i, j) takes planes k0..k0+ZB-1
+// of its column and keeps v along the column in registers (as T, zero on the
+// walls, odd reflection beyond them), so each z-neighbour is loaded once per
+// column segment instead of once per node; nodes at least r + 1 from the x
+// and y walls load their x- and y-neighbours directly, nearer ones through
+// the reflection.  The same arithmetic per node as first_step_node.
+template <typename T, int P, int ZB>
+__global__ __launch_bounds__(kBlockX *kBlockY) void first_step3d_zcol_kernel(
+    StepGeom g, const double *__restrict__ v, T *__restrict__ W0, T *__restrict__ W1,
+    double *__restrict__ acc, const T *__restrict__ c2, const T *__restrict__ f, double g0, double w0,
+    double w1) {
+  constexpr int R = P / 2;
+  const int i = blockIdx.x * kBlockX + threadIdx.x;
+  const int j = blockIdx.y * kBlockY + threadIdx.y;
+  const int k0 = blockIdx.z * ZB;
+  if (i > g.nx || j > g.ny) return;
+  const bool col_wall = i == 0 || i == g.nx || j == 0 || j == g.ny;
+  const int64_t base = (int64_t)i + (int64_t)j * g.sy;
+  T col[ZB + 2 * R];
+#pragma unroll
+  for (int t = 0; t < ZB + 2 * R; ++t) {
+    int k = k0 - R + t;
+    T sgn = T(1);
+    if (k < 0) { k = -k; sgn = -sgn; } else if (k > g.nz) { k = 2 * g.nz - k; sgn = -sgn; }
+    // planes past the reflection range feed no computed node
+    col[t] = (col_wall || k <= 0 || k >= g.nz) ? T(0) : sgn * static_cast<T>(v[base + (int64_t)k * g.sz]);
+  }
+  auto val = [&](int a, int b, int d) -> T {  // x- or y-neighbour near a wall
+    T sg = T(1);
+    if (a < 0) { a = -a; sg = -sg; } else if (a > g.nx) { a = 2 * g.nx - a; sg = -sg; }
+    if (b < 0) { b = -b; sg = -sg; } else if (b > g.ny) { b = 2 * g.ny - b; sg = -sg; }
+    if (a == 0 || a == g.nx || b == 0 || b == g.ny) return T(0);
+    return sg * static_cast<T>(v[(int64_t)a + (int64_t)b * g.sy + (int64_t)d * g.sz]);
+  };
+  const bool far = i > R && i < g.nx - R && j > R && j < g.ny - R;
+  const Coef<T> c = coef_of<T>(g);
+#pragma unroll
+  for (int t = 0; t < ZB; ++t) {
+    const int k = k0 + t;
+    if (k > g.nz) break;
+    const int64_t idx = base + (int64_t)k * g.sz;
+    if (col_wall || k == 0 || k == g.nz) {
+      W0[idx] = T(0);
+      W1[idx] = T(0);
+      acc[idx] = 0.0;
+      continue;
+    }
+    auto nb = [&](int di, int dj) -> T {
+      return far ? static_cast<T>(v[idx + di + (int64_t)dj * g.sy]) : val(i + di, j + dj, k);
+    };
+    const T u0 = col[t + R];
+    T r;
+    if constexpr (P == 2) {
+      r = c.kx * (nb(-1, 0) + nb(1, 0)) + c.ky * (nb(0, -1) + nb(0, 1));
+      r += c.kz * (col[t + R - 1] + col[t + R + 1]);
+    } else {
+      r = c.kx * (T(16) * (nb(-1, 0) + nb(1, 0)) - (nb(-2, 0) + nb(2, 0))) +
+          c.ky * (T(16) * (nb(0, -1) + nb(0, 1)) - (nb(0, -2) + nb(0, 2)));
+      r += c.kz * (T(16) * (col[t + R - 1] + col[t + R + 1]) - (col[t + R - 2] + col[t + R + 2]));
+    }
+    const T lap = r - c.kc * u0;
+    const T c2v = c2 ? c2[idx] : static_cast<T>(g.c2const);
+    T u1 = u0 + c2v * lap;
+    if (f) u1 += static_cast<T>(g0) * f[idx];
+    W0[idx] = u0;
+    W1[idx] = u1;
+    acc[idx] = w0 * static_cast<double>(u0) + w1 * static_cast<double>(u1);
+  }
+}
+
 // Batched first step of 2-D problems: flat node blocks, problem found from
 // the block offsets (ascending).
 template <typename T, int P>
@@ -627,9 +697,18 @@ unsigned flat_blocks(int64_t n) {
 template <typename T, int DIM, int P>
 void first_step_typed(const StepGeom &g, const double *v, void *W0, void *W1, double *acc, const void *c2,
                       const void *f, double g0, double w0, double w1, hipStream_t s) {
-  first_step_kernel<T, DIM, P><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(
-      g, v, static_cast<T *>(W0), static_cast<T *>(W1), acc, static_cast<const T *>(c2),
-      static_cast<const T *>(f), g0, w0, w1);
+  if constexpr (DIM == 3) {
+    constexpr int ZB = 8;
+    dim3 grid((unsigned)((g.nx + 1 + kBlockX - 1) / kBlockX), (unsigned)((g.ny + 1 + kBlockY - 1) / kBlockY),
+              (unsigned)((g.nz + 1 + ZB - 1) / ZB));
+    first_step3d_zcol_kernel<T, P, ZB><<<grid, dim3(kBlockX, kBlockY), 0, s>>>(
+        g, v, static_cast<T *>(W0), static_cast<T *>(W1), acc, static_cast<const T *>(c2),
+        static_cast<const T *>(f), g0, w0, w1);
+  } else {
+    first_step_kernel<T, DIM, P><<<node_grid(g), dim3(kBlockX, kBlockY), 0, s>>>(
+        g, v, static_cast<T *>(W0), static_cast<T *>(W1), acc, static_cast<const T *>(c2),
+        static_cast<const T *>(f), g0, w0, w1);
+  }
 }
 
 template <typename T, int DIM, int P>
