@@ -493,7 +493,8 @@ def run_cube_block(args, dev):
     n, order = args.n, args.order
     t_setup = time.perf_counter()
     w = wl.cube_inclusion(n=n, order=order)
-    s = Solver(3, (n, n, n), order=order, precision=args.precision, restart=2)
+    gmres = args.solver == "gmres"
+    s = Solver(3, (n, n, n), order=order, precision=args.precision, restart=args.restart if gmres else 2)
     s.set_tuning(args.kernel, args.kblock, args.tile)
     s.set_c2(w["c2"])
     s.set_source(w["f"])
@@ -505,7 +506,8 @@ def run_cube_block(args, dev):
     pts_per_apply = unknowns * tp["nt"] * tp["periods"]
 
     def one_step():
-        return s.solve(method="cg", rtol=0.0, maxit=args.iters)
+        return s.solve(method=args.solver, rtol=0.0, maxit=args.iters,
+                       restart=args.restart if gmres else 2)
 
     for i in range(args.warmup):
         t0 = time.perf_counter()
@@ -519,7 +521,7 @@ def run_cube_block(args, dev):
     for i in range(args.steps):
         x, info = one_step()
         infos.append(info)
-        log(f"step {i + 1}/{args.steps}: {info['iters']} CG iterations, {info['applies']} applies, "
+        log(f"step {i + 1}/{args.steps}: {info['iters']} {args.solver} iterations, {info['applies']} applies, "
             f"rel_res {info['rel_res']:.3e}, {info['seconds']:.2f}s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -555,8 +557,11 @@ def run_cube_block(args, dev):
         "config": {
             "workload": f"cube {n}^3, order {order}, c = 1 with a c = 1.5 ball, omega = {w['omega']:g}, "
                         f"point-like Gaussian source; {args.precision} state, FP64 filter and Krylov; "
-                        f"step = {args.iters} CG iterations (1/c^2 inner product) from v = 0",
-            "n": n, "order": order, "omega": w["omega"], "nt": tp["nt"], "solver": "cg",
+                        f"step = {args.iters} "
+                        + (f"GMRES({args.restart}) iterations" if gmres else "CG iterations (1/c^2 inner product)")
+                        + " from v = 0",
+            "n": n, "order": order, "omega": w["omega"], "nt": tp["nt"], "solver": args.solver,
+            "restart": args.restart if gmres else None,
             "iterations_per_step": args.iters, "state_precision": args.precision,
             "filter_and_krylov_precision": "fp64", "kernel": tun["kernel"], "steps_per_launch": tun["kblock"],
             "tile_rows": tun["tile"], "owned_tile": list(tun["owned"]),

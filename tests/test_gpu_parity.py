@@ -717,6 +717,33 @@ def test_random_speed_square_2048_sampled(torch, prec):
 # sine mode (3, 2, 5), since 4th-order points must stay within about 280
 # nodes of a corner to keep the oracle's sub-box (the domain of dependence,
 # half-width 272 nodes) small, and the source's waves do not reach there.
+def test_gmres_on_the_512_cube_minimises_the_residual_over_cg(torch):
+    """GMRES(50) and CG, 30 iterations each from v = 0 on the 512^3 inclusion
+    cube (FP32 state, FP64 Krylov vectors), search the same Krylov space
+    K_30(A, b); GMRES minimises the Euclidean residual over it, so its true
+    residual is at most CG's (up to the FP32 rounding of the applications),
+    and its Givens estimate of the residual is the true residual."""
+    _say("[512^3 gmres] GMRES(50) against CG at 30 iterations")
+    w = wl.cube_inclusion(n=512, order=2)
+    s = _solver(3, (512, 512, 512), 2, "fp32", restart=50)
+    s.set_c2(w["c2"])
+    s.set_source(w["f"])
+    s.set_frequency(w["omega"])
+    del w
+    b = s.apply(s.new(), with_forcing=True)
+    nb = torch.linalg.norm(b).item()
+    xg, ig = s.solve(method="gmres", rtol=0.0, maxit=30, restart=50)
+    rg = torch.linalg.norm(b - s.apply_A(xg)).item() / nb
+    del xg
+    xc, ic = s.solve(method="cg", rtol=0.0, maxit=30)
+    rc = torch.linalg.norm(b - s.apply_A(xc)).item() / nb
+    del xc
+    _say(f"    GMRES {rg:.6e} (estimate {ig['rel_res']:.6e}), CG {rc:.6e}")
+    assert ig["iters"] == 30 and ic["iters"] == 30
+    assert rg <= rc * (1 + 1e-4)
+    assert ig["rel_res"] == pytest.approx(rg, rel=1e-3)
+
+
 CUBE_CASES = [
     (2, "fp64", 3, "random", [(2, 3, 1), (509, 1, 510), (60, 30, 5), (256, 256, 256), (100, 40, 400)]),
     (4, "fp64", 2, "random", [(2, 3, 1), (60, 30, 5), (70, 40, 20)]),
