@@ -95,7 +95,7 @@ struct Prefetch3d {
 };
 
 // K leapfrog steps of the owned planes [z0, z1) of tile (tx, ty).
-template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR, bool INNER>
+template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR, bool VA, bool INNER>
 __device__ __forceinline__ void advance_column_impl(
     const StepGeom &g, int tx, int ty, int z0, int z1, const T *__restrict__ in_prev, const T *__restrict__ in_cur,
     T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc, const T *__restrict__ c2g,
@@ -246,6 +246,20 @@ __device__ __forceinline__ void advance_column_impl(
     }
     if (it + PD < nit) nsg[slot] = load_plane(slot_c, zp + PD);
     if constexpr (!ACP) load_acc(AC, zo, RS);
+    // VA: the last pass of A v (out = v - acc) loads v of the output plane
+    // here, so that its latency hides behind the steps (loaded at the store
+    // it stalls every row: 25% longer passes in FP32, 43% in FP64).  A
+    // separate instantiation: the same load in the kernel of every pass,
+    // behind a test of the mode, made all passes 16% slower.
+    [[maybe_unused]] double VV[VA ? RS : 1];
+    if constexpr (VA) {
+      const bool live = out_plane && !zwall;
+#pragma unroll
+      for (int q = 0; q < RS; ++q) {
+        VV[q] = 0.0;
+        if (live && ((own & ~wall) >> q) & 1u) VV[q] = ld_at(v + ob, off[q]);
+      }
+    }
     // y-halo: every level's centre plane (slot r) is what its step needs
     const int hb = it & 1;
 #pragma unroll
@@ -360,6 +374,7 @@ __device__ __forceinline__ void advance_column_impl(
         st_at(out_prev + ob, e, WV[q][PP::off(K - 1) + R]);
         if (mode == ACCUMULATE) st_at(acc + ob, e, a);
         else if (mode == FINAL_FILTER) st_at(out + ob, e, a);
+        else if constexpr (VA) st_at(out + ob, e, VV[VA ? q : 0] - a);
         else st_at(out + ob, e, ld_at(v + ob, e) - a);
       }
     }
@@ -372,7 +387,7 @@ __device__ __forceinline__ void advance_column_impl(
   }
 }
 
-template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR>
+template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR, bool VA>
 __global__ __launch_bounds__(64 * NW) void block3d_steps_kernel(
     StepGeom g, int tiles_x, int tiles_xy, int zlen, int tiles_total, const T *__restrict__ in_prev,
     const T *__restrict__ in_cur, T *__restrict__ out_prev, T *__restrict__ out_cur, double *__restrict__ acc,
@@ -392,10 +407,10 @@ __global__ __launch_bounds__(64 * NW) void block3d_steps_kernel(
   const int x0 = tx * OX - H, y0 = ty * OY - H;
   const bool inner = x0 >= 1 && x0 + 63 <= g.nx - 1 && y0 >= 1 && y0 + NW * RS - 1 <= g.ny - 1;
   if (inner)
-    advance_column_impl<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, true>(
+    advance_column_impl<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, VA, true>(
         g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur, acc, c2g, fg, coef, mode, v, out, halo);
   else
-    advance_column_impl<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, false>(
+    advance_column_impl<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, VA, false>(
         g, tx, ty, z0, z1, in_prev, in_cur, out_prev, out_cur, acc, c2g, fg, coef, mode, v, out, halo);
 }
 
@@ -417,7 +432,7 @@ struct Rows3d {
 // Work-groups of one kernel that the current device keeps resident at once:
 // CUs times the groups one CU holds (its registers and LDS decide: one
 // 16-wave FP32 group, two 8-wave ones).
-template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR>
+template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE, bool CVAR, bool VA>
 int block3d_resident() {
   static std::atomic<int> cache[64];
   int dev = 0;
@@ -427,7 +442,7 @@ int block3d_resident() {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FORCE, CVAR>, 64 * NW, 0) != hipSuccess ||
+            &per, block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, VA>, 64 * NW, 0) != hipSuccess ||
         per < 1)
       per = 1;
     r = cus * per;
@@ -488,9 +503,9 @@ hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in
     const T *cc = static_cast<const T *>(c2);
     const T *ff = static_cast<const T *>(f);
     hipError_t err = hipSuccess;
-    auto go = [&](auto force_c, auto cvar_c) {
-      constexpr bool FO = decltype(force_c)::value, CV = decltype(cvar_c)::value;
-      const int zlen = block3d_zlen(g.nz, tiles_xy, H, block3d_resident<T, P, K, RS, NW, PD, ACP, FO, CV>());
+    auto go = [&](auto force_c, auto cvar_c, auto va_c) {
+      constexpr bool FO = decltype(force_c)::value, CV = decltype(cvar_c)::value, VA = decltype(va_c)::value;
+      const int zlen = block3d_zlen(g.nz, tiles_xy, H, block3d_resident<T, P, K, RS, NW, PD, ACP, FO, CV, VA>());
       const int nseg = (g.nz + 1 + zlen - 1) / zlen;
       const int64_t tiles64 = (int64_t)tiles_xy * nseg;
       if (tiles64 > (int64_t)1 << 30) {
@@ -499,15 +514,19 @@ hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in
       }
       const int tiles = (int)tiles64;
       const int blocks = ((tiles + 7) / 8) * 8;  // whole rounds over the 8 XCDs
-      block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FO, CV><<<dim3(blocks), dim3(64 * NW), 0, s>>>(
+      block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FO, CV, VA><<<dim3(blocks), dim3(64 * NW), 0, s>>>(
           g, tiles_x, tiles_xy, zlen, tiles, ip, ic, op, oc, acc, cc, ff, coef, mode, v, out);
     };
     using yes = std::true_type;
     using no = std::false_type;
-    if (f && c2) go(yes{}, yes{});
-    else if (f) go(yes{}, no{});
-    else if (c2) go(no{}, yes{});
-    else go(no{}, no{});
+    // the last pass of A v (never forced) has its own instantiation
+    const bool va = mode == FINAL_A;
+    if (f && c2) go(yes{}, yes{}, no{});
+    else if (f) go(yes{}, no{}, no{});
+    else if (c2 && va) go(no{}, yes{}, yes{});
+    else if (c2) go(no{}, yes{}, no{});
+    else if (va) go(no{}, no{}, yes{});
+    else go(no{}, no{}, no{});
     if (err != hipSuccess) return err;
     return hipGetLastError();
   }
