@@ -478,15 +478,25 @@ template <typename T, int P, int K, int RS, int NW, int PD, bool ACP, bool FORCE
 int block3d_resident() {
   static std::atomic<int> cache[64];
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
   int r = cache[dev].load(std::memory_order_relaxed);
   if (r == 0) {
+    // a failed query falls back to one group per CU of an MI355X; its error is
+    // cleared so that the launch check after it does not report it
     int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+      (void)hipGetLastError();
+      cus = 256;
+    }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per, block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FORCE, CVAR, VA>, 64 * NW, 0) != hipSuccess ||
-        per < 1)
+        per < 1) {
+      (void)hipGetLastError();
       per = 1;
+    }
     r = cus * per;
     cache[dev].store(r, std::memory_order_relaxed);
   }
