@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before timing")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
-                    help="state precision (default: fp64, fp32 for --mode kernel on the cube)")
+                    help="state precision (default: fp32 on the cube except for --iters 0, fp64 otherwise)")
     ap.add_argument("--workload", choices=["square", "cube"], default="cube",
                     help="cube: 512^3 inclusion (default; --mode solve or kernel); square: 2048^2 random c^2")
     ap.add_argument("--order", type=int, choices=[2, 4], default=0, help="stencil order (default: 4 square, 2 cube)")
@@ -89,10 +89,12 @@ def parse():
     ap.add_argument("--maxit", type=int, default=0,
                     help="iteration cap of a solve to the residual target (0: 40000 square, 2000 cube)")
     ap.add_argument("--iters", type=int, default=100,
-                    help="cube: CG iterations per timed step (0: one solve towards the residual target)")
+                    help="cube: Krylov iterations per timed step, CG or --solver gmres "
+                         "(0: one solve towards the residual target)")
     ap.add_argument("--no-square", dest="square", action="store_false", default=True,
                     help="cube: skip the 2048^2 FP64 time-to-residual solve reported beside the line")
-    ap.add_argument("--kernel", default="auto", help="time-stepping kernel family (auto, node, blocked_2d)")
+    ap.add_argument("--kernel", default="auto",
+                    help="time-stepping kernel family (auto, node, blocked_2d, zcol_3d, blocked_3d)")
     ap.add_argument("--kblock", type=int, default=0, help="leapfrog steps per launch (0 = automatic)")
     ap.add_argument("--tile", type=int, default=0, help="tile parameter of the kernel family (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="let the library time every variant first")
