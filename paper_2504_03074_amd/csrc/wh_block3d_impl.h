@@ -74,13 +74,13 @@ constexpr int block3d_lds_bytes() {
 // where it fits beside the halo; loading f inside the step loop stalls every
 // step on its loads (512^3, 2nd order, constant c^2: 1547 -> 1316 us per
 // pass; 4th order: 2443 -> 2267 us with variable c^2, 2386 -> 2208 us with
-// constant c^2).  Not
-// where the staging registers would cost the second staged plane (FP32 2nd
-// order with variable c^2: 1733 us with the loads in the steps, 1768 us with
-// the ring and one plane staged) nor in FP64, whose rings leave no registers.
-template <typename T, int P, int K, int NW, int RS, int PD, bool FORCE, bool CVAR>
+// constant c^2).  The FP32 2nd-order kernel with variable c^2 has registers
+// for the ring only without staging the accumulator ahead (1731 -> 1661 us;
+// with the ring and one plane staged instead: 1768 us).  Not in FP64, whose
+// rings leave no registers for the staging.
+template <typename T, int P, int K, int NW, int RS, int PD, bool ACP, bool FORCE, bool CVAR>
 constexpr bool block3d_fring() {
-  return FORCE && sizeof(T) == 4 && (!CVAR || PD == 1) &&
+  return FORCE && sizeof(T) == 4 && (!CVAR || PD == 1 || !ACP) &&
          block3d_lds_bytes<T, P, K, NW>() + (K * (P / 2) + 1) * NW * RS * 64 * (int)sizeof(T) <= kBlock3dMaxLds;
 }
 
@@ -119,7 +119,7 @@ __device__ __forceinline__ void advance_column_impl(
   using PP = Pipe3d<P, K>;
   constexpr int R = PP::R;
   constexpr int H = PP::H;
-  constexpr bool FRING = block3d_fring<T, P, K, NW, RS, PD, FORCE, CVAR>();
+  constexpr bool FRING = block3d_fring<T, P, K, NW, RS, PD, ACP, FORCE, CVAR>();
   constexpr int LF = K * R + 1;  // forcing planes in the ring
   constexpr int OX = 64 - 2 * H;
   constexpr int OY = NW * RS - 2 * H;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(64 * NW) void block3d_steps_kernel(
   constexpr int OX = 64 - 2 * H;
   constexpr int OY = NW * RS - 2 * H;
   __shared__ T halo[2][K][NW][2][P / 2][64];
-  __shared__ T fring[block3d_fring<T, P, K, NW, RS, PD, FORCE, CVAR>() ? K * (P / 2) + 1 : 1][NW * RS][64];
+  __shared__ T fring[block3d_fring<T, P, K, NW, RS, PD, ACP, FORCE, CVAR>() ? K * (P / 2) + 1 : 1][NW * RS][64];
   const int tile = xcd_tile_order(blockIdx.x, gridDim.x);
   if (tile >= tiles_total) return;
   const int seg = tile / tiles_xy;
@@ -557,7 +557,10 @@ hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in
     hipError_t err = hipSuccess;
     auto go = [&](auto force_c, auto cvar_c, auto va_c) {
       constexpr bool FO = decltype(force_c)::value, CV = decltype(cvar_c)::value, VA = decltype(va_c)::value;
-      const int zlen = block3d_zlen(g.nz, tiles_xy, H, block3d_resident<T, P, K, RS, NW, PD, ACP, FO, CV, VA>());
+      // forced variable-speed passes trade the accumulator staging for the
+      // forcing ring (the registers hold one or the other)
+      constexpr bool ACPv = ACP && !(FO && CV);
+      const int zlen = block3d_zlen(g.nz, tiles_xy, H, block3d_resident<T, P, K, RS, NW, PD, ACPv, FO, CV, VA>());
       const int nseg = (g.nz + 1 + zlen - 1) / zlen;
       const int64_t tiles64 = (int64_t)tiles_xy * nseg;
       if (tiles64 > (int64_t)1 << 30) {
@@ -566,7 +569,7 @@ hipError_t launch3d_typed(const StepGeom &g, const void *in_prev, const void *in
       }
       const int tiles = (int)tiles64;
       const int blocks = ((tiles + 7) / 8) * 8;  // whole rounds over the 8 XCDs
-      block3d_steps_kernel<T, P, K, RS, NW, PD, ACP, FO, CV, VA><<<dim3(blocks), dim3(64 * NW), 0, s>>>(
+      block3d_steps_kernel<T, P, K, RS, NW, PD, ACPv, FO, CV, VA><<<dim3(blocks), dim3(64 * NW), 0, s>>>(
           g, tiles_x, tiles_xy, zlen, tiles, ip, ic, op, oc, acc, cc, ff, coef, mode, v, out);
     };
     using yes = std::true_type;
