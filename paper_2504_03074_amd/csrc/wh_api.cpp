@@ -326,8 +326,9 @@ Tuning resolve_tuning(const wh_ctx *c) {
     if (c->dim == 2)
       return {WH_KERNEL_BLOCKED_2D, default_kblock(c->order, fp32), wh::block_default_rows(fp32, c->order)};
     // the fastest measured per state type and order; FP64 p = 2 at K = 4 and
-    // FP64 p = 4 at K >= 3 run out of registers and spill
-    const int k3 = c->order == 2 ? (fp32 ? 4 : 3) : (fp32 ? 3 : 2);
+    // FP64 p = 4 at K >= 3 run out of registers and spill; FP32 p = 4 at K = 2
+    // stages two planes ahead, which makes it faster per step than K = 3
+    const int k3 = c->order == 2 ? (fp32 ? 4 : 3) : 2;
     if (tuning_supported(c, WH_KERNEL_BLOCKED_3D, k3, 0))
       return {WH_KERNEL_BLOCKED_3D, k3, wh::block3d_default_rows(fp32, c->order, k3)};
     return {WH_KERNEL_NODE, 1, 0};

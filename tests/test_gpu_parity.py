@@ -748,7 +748,7 @@ CUBE_CASES = [
     (2, "fp64", 3, "random", [(2, 3, 1), (509, 1, 510), (60, 30, 5), (256, 256, 256), (100, 40, 400)]),
     (4, "fp64", 2, "random", [(2, 3, 1), (60, 30, 5), (70, 40, 20)]),
     (2, "fp32", 4, "rhs", [(256, 256, 77), (250, 262, 90), (270, 240, 70), (256, 256, 110), (60, 30, 5)]),
-    (4, "fp32", 3, "mode", [(60, 30, 5), (2, 3, 1), (80, 100, 40)]),
+    (4, "fp32", 2, "mode", [(60, 30, 5), (2, 3, 1), (80, 100, 40)]),
 ]
 
 
