@@ -136,10 +136,15 @@ __device__ __forceinline__ void advance_column_impl(
   uint32_t off[RS];
   T sgn[RS];
   uint32_t own = 0, wall = 0;
-  // offset of the nearest node owned by the tile (the node itself if it is
-  // owned): the accumulator and v loads read there, unconditionally, and use
-  // the value only at owned interior nodes.  A load behind a per-lane branch
-  // makes the compiler drain every outstanding load before the next plane's.
+  // UNC (unforced accumulating passes that stage the accumulator ahead): every
+  // load unconditional, so that the loop-head waits can count them (a load
+  // behind a test makes the compiler drain every outstanding load before the
+  // staged plane is used).  The accumulator is then read at the nearest node
+  // owned by the tile (the node itself if it is owned) and used only at owned
+  // interior nodes.  The other instantiations (forced passes, the last pass
+  // of A v, FP64 with one plane staged) measured the same or slower that way and
+  // keep their loads behind the tests.
+  constexpr bool UNC = ACP && !VA && !FORCE;
   const uint32_t cx = (uint32_t)min(max(gx, tx * OX), min(tx * OX + OX - 1, g.nx));
   const int cy_lo = ty * OY, cy_hi = min(ty * OY + OY - 1, g.ny);
   {
@@ -197,9 +202,19 @@ __device__ __forceinline__ void advance_column_impl(
   // the one entering) is staged together with that plane
   double NAC[PD][ACP ? RS : 1];
   auto load_acc = [&](auto &dst, int zo, int nq) {
-    const int64_t ob = (int64_t)min(max(zo, 0), g.nz) * sz;  // any plane where zo is not stored
+    if constexpr (UNC) {
+      const int64_t ob = (int64_t)min(max(zo, 0), g.nz) * sz;  // any plane where zo is not stored
 #pragma unroll
-    for (int q = 0; q < nq; ++q) dst[q] = ld_at(acc + ob, near_off(q));
+      for (int q = 0; q < nq; ++q) dst[q] = ld_at(acc + ob, near_off(q));
+    } else {
+      const bool live = zo >= z0 && zo < z1 && zo != 0 && zo != g.nz;
+      const int64_t ob = (int64_t)zo * sz;
+#pragma unroll
+      for (int q = 0; q < nq; ++q) {
+        dst[q] = 0.0;
+        if (live && ((own & ~wall) >> q) & 1u) dst[q] = ld_at(acc + ob, off[q]);
+      }
+    }
   };
   auto load_plane = [&](auto slot_c, int zl) -> T {
     constexpr int slot = decltype(slot_c)::value;
@@ -225,7 +240,9 @@ __device__ __forceinline__ void advance_column_impl(
     }
   }
   nsg[0] = load_plane(std::integral_constant<int, 0>{}, z0 - H);
-  if constexpr (PD == 2) nsg[PD - 1] = load_plane(std::integral_constant<int, PD - 1>{}, z0 - H + 1);
+  if constexpr (PD == 2) {
+    if (UNC || nit > 1) nsg[PD - 1] = load_plane(std::integral_constant<int, PD - 1>{}, z0 - H + 1);
+  }
 
   auto iterate = [&](int it, auto slot_c) {
     constexpr int slot = decltype(slot_c)::value;
@@ -286,11 +303,9 @@ __device__ __forceinline__ void advance_column_impl(
 #pragma unroll
       for (int q = 0; q < RS; ++q) AC[q] = NAC[slot][q];
     }
-    // unconditional (past the column's end the reflection still gives a
-    // valid plane, loaded and never used): with the loads behind a test the
-    // compiler cannot count them and waits for all loads in flight, including
-    // those of the other slot, before each staged plane
-    nsg[slot] = load_plane(slot_c, zp + PD);
+    // with UNC past the column's end too: the reflection still gives a valid
+    // plane, loaded and never used
+    if (UNC || it + PD < nit) nsg[slot] = load_plane(slot_c, zp + PD);
     if constexpr (!ACP) load_acc(AC, zo, RS);
     // VA: the last pass of A v (out = v - acc) loads v of the output plane
     // here, so that its latency hides behind the steps (loaded at the store
@@ -299,9 +314,12 @@ __device__ __forceinline__ void advance_column_impl(
     // behind a test of the mode, made all passes 16% slower.
     [[maybe_unused]] double VV[VA ? RS : 1];
     if constexpr (VA) {
-      const int64_t obv = (int64_t)min(max(zo, 0), g.nz) * sz;
+      const bool live = out_plane && !zwall;
 #pragma unroll
-      for (int q = 0; q < RS; ++q) VV[q] = ld_at(v + obv, near_off(q));
+      for (int q = 0; q < RS; ++q) {
+        VV[q] = 0.0;
+        if (live && ((own & ~wall) >> q) & 1u) VV[q] = ld_at(v + ob, off[q]);
+      }
     }
     // y-halo: every level's centre plane (slot r) is what its step needs
     const int hb = it & 1;
