@@ -129,6 +129,7 @@ __device__ __forceinline__ void advance_tile_impl(
   T A[RS], B[RS], C2[RS], F[FL ? 1 : RS];
   double ACC[RS];
   uint32_t own = 0;  // bit q: row q of this lane is an owned interior node
+  [[maybe_unused]] uint32_t own_wall = 0;  // bit q: an owned wall node (outputs 0)
 
   // Inner tiles (tile and halo strictly inside the walls, the usual case)
   // need no reflection and hold no wall node: every row is addressed by one
@@ -158,6 +159,13 @@ __device__ __forceinline__ void advance_tile_impl(
     const int ix = reflect(gx, g.nx, sx);
     const bool col_owned = col_in && gx <= g.nx;
     const bool col_wall = ix == 0 || ix == g.nx;
+    // Every load here is unconditional (a load behind a per-lane test makes
+    // the compiler drain all loads in flight at the next wait): the
+    // accumulator is read at the nearest node owned by the tile (the node
+    // itself if it is owned; never a node another tile writes) and used only
+    // at owned interior nodes; owned wall nodes get their zeros at the end.
+    const int64_t ax = min(max(gx, x0), min(x0 + OX - 1, g.nx));
+    const int ay_lo = y0, ay_hi = min(y0 + OY - 1, g.ny);
 #pragma unroll
     for (int q = 0; q < RS; ++q) {
       float s = sx;
@@ -170,19 +178,12 @@ __device__ __forceinline__ void advance_tile_impl(
       C2[q] = CVAR ? c2g[id] : static_cast<T>(g.c2const);
       if constexpr (FL) fsh[wave * RS + q][lane] = sg * fg[id];
       else F[q] = FORCE ? sg * fg[id] : T(0);
+      ACC[q] = acc[ax + (int64_t)min(max(gy, ay_lo), ay_hi) * g.sy];
       const int r = wave * RS + q;
       const bool in_tile = col_owned && r >= H && r < H + OY && gy <= g.ny;
       const bool wall = col_wall || iy == 0 || iy == g.ny;
-      ACC[q] = 0.0;
-      if (in_tile && !wall) {
-        own |= 1u << q;
-        ACC[q] = acc[id];
-      } else if (in_tile) {
-        // wall node owned by this tile: its outputs are exactly 0
-        out_prev[id] = T(0);
-        out_cur[id] = T(0);
-        if (mode != ACCUMULATE) out[id] = 0.0;
-      }
+      if (in_tile && !wall) own |= 1u << q;
+      else if (in_tile) own_wall |= 1u << q;
     }
   }
 
@@ -272,8 +273,15 @@ __device__ __forceinline__ void advance_tile_impl(
   }
 #pragma unroll
   for (int q = 0; q < RS; ++q) {
-    if (!((own >> q) & 1u)) continue;
     const int64_t id = (int64_t)gx + (int64_t)(gy0 + q) * g.sy;  // owned nodes need no reflection
+    if ((own_wall >> q) & 1u) {
+      // wall node owned by this tile: its outputs are exactly 0
+      out_prev[id] = T(0);
+      out_cur[id] = T(0);
+      if (mode != ACCUMULATE) out[id] = 0.0;
+      continue;
+    }
+    if (!((own >> q) & 1u)) continue;
     out_cur[id] = odd ? B[q] : A[q];
     out_prev[id] = odd ? A[q] : B[q];
     if (mode == ACCUMULATE) acc[id] = ACC[q];
