@@ -23,6 +23,10 @@ struct Coef {
   T kx, ky, kz, kc;
 };
 
+// Read by the first steps in place of a neighbour that lies on a wall (its
+// value is 0 there); never written.
+__device__ double kZeroNode = 0.0;
+
 // Value at a node index that may lie up to 2 nodes beyond a wall: odd
 // reflection u(-j) = -u(j), u(n+j) = -u(n-j).  Wall nodes themselves hold 0 in
 // every state array.
@@ -79,6 +83,9 @@ __device__ __forceinline__ T stencil(const T *__restrict__ W, int i, int j, int 
 
 // Same stencil applied to a caller array whose wall values must be ignored
 // (treated as 0): used by the first step, which reads the iterate v directly.
+// The load address is selected per lane (the reflected node, or kZeroNode
+// for a wall node), so that no load sits behind a branch: a load behind a
+// per-lane test makes the compiler drain all loads in flight at its wait.
 template <typename T, int DIM, int P>
 __device__ __forceinline__ T stencil_from_v(const double *__restrict__ v, int i, int j, int k,
                                             const StepGeom &g, const Coef<T> &c) {
@@ -89,9 +96,9 @@ __device__ __forceinline__ T stencil_from_v(const double *__restrict__ v, int i,
     if (DIM == 3) {
       if (d < 0) { d = -d; s = -s; } else if (d > g.nz) { d = 2 * g.nz - d; s = -s; }
     }
-    const bool wall = a == 0 || a == g.nx || b == 0 || b == g.ny || (DIM == 3 && (d == 0 || d == g.nz));
-    if (wall) return T(0);
-    return s * static_cast<T>(v[(int64_t)a + (int64_t)b * g.sy + (int64_t)d * g.sz]);
+    const bool wall = a <= 0 || a >= g.nx || b <= 0 || b >= g.ny || (DIM == 3 && (d <= 0 || d >= g.nz));
+    const double *p = wall ? &kZeroNode : v + ((int64_t)a + (int64_t)b * g.sy + (int64_t)d * g.sz);
+    return (wall ? T(1) : s) * static_cast<T>(*p);
   };
   const T w0 = val(i, j, k);
   if (P == 2) {
@@ -148,10 +155,6 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void first_step_kernel(
   if (i > g.nx || j > g.ny) return;
   first_step_node<T, DIM, P>(g, i, j, k, v, W0, W1, acc, c2, f, g0, w0, w1);
 }
-
-// Read by the 3-D first step in place of a neighbour that lies on a wall (its
-// value is 0 there); never written.
-__device__ double kZeroNode = 0.0;
 
 // 3-D first step with z coarsening: thread (i, j) takes planes k0..k0+ZB-1
 // of its column and keeps v along the column in registers (as T, zero on the
