@@ -10,6 +10,7 @@
 #include <cstdint>
 
 #include "wh_internal.h"
+#include "wh_xcd.h"
 
 namespace wh {
 namespace {
@@ -173,11 +174,7 @@ __global__ __launch_bounds__(kBlockX *kBlockY) void first_step3d_zcol_kernel(
     double *__restrict__ acc, const T *__restrict__ c2, const T *__restrict__ f, double g0, double w0,
     double w1) {
   constexpr int R = P / 2;
-  // linear dispatch index L (x fastest; gridDim.x is a multiple of 8, so L % 8
-  // is the XCD) -> block lb: XCD x takes blocks x * per .. x * per + per - 1
-  const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  const int64_t per = (int64_t)gridDim.x * gridDim.y / 8;
-  const int64_t lb64 = (L % 8) * per + L / 8;
+  const int64_t lb64 = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
   if (lb64 >= nblk) return;
   const int lb = (int)lb64;
   const int bx = lb % gx, rest = lb / gx, by = rest % gy, bz = rest / gy;
@@ -746,11 +743,7 @@ void first_step_typed(const StepGeom &g, const double *v, void *W0, void *W1, do
     constexpr int ZB = 4;
     const int gx = (g.nx + kBlockX) / kBlockX, gy = (g.ny + kBlockY) / kBlockY, gz = (g.nz + ZB) / ZB;
     const int nblk = gx * gy * gz;  // at most about nodes / 12 < 2^30 (nodes <= 2^33)
-    // whole rounds over the 8 XCDs; a launch dimension holds at most 2^32
-    // work-items, so large launches use rows of 2^16 work-groups
-    const int64_t padded = ((int64_t)nblk + 7) / 8 * 8;
-    const dim3 grid = padded <= (1 << 24) ? dim3((unsigned)padded)
-                                          : dim3(1u << 16, (unsigned)((padded + (1 << 16) - 1) >> 16));
+    const dim3 grid = xcd_grid(nblk);
     const dim3 block(kBlockX, kBlockY);
     const T *c2t = static_cast<const T *>(c2), *ft = static_cast<const T *>(f);
     T *W0t = static_cast<T *>(W0), *W1t = static_cast<T *>(W1);

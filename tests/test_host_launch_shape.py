@@ -1,7 +1,8 @@
-"""Host logic of the 3-D blocked launch that needs no GPU: how many z
-segments each tile column is split into.  A small host program that includes
-the kernel header is compiled with hipcc and run on the CPU; it calls only
-the segment-length chooser (no device code runs).
+"""Host logic of the 3-D launches that needs no GPU: how many z segments each
+tile column of the blocked kernel is split into, and the XCD-contiguous
+numbering of the first step's work-groups.  Small host programs that include
+the kernel headers are compiled with hipcc and run on the CPU; they call only
+host functions (no device code runs).
 
 The chooser models a launch as rounds of `resident` equal work-groups, each
 loading its segment plus 2H planes, and takes the fewest segments within 3%
@@ -98,3 +99,58 @@ def test_matches_the_model_and_its_bounds(zlen):
         assert 1 <= z <= planes
         if planes >= max(4 * H, 8):
             assert z >= max(4 * H, 8), (nz, tiles, H, resident, z)
+
+
+XCD_PROGRAM = r"""
+#include "wh_xcd.h"
+#include <cstdio>
+#include <vector>
+int main() {
+  long long nblk;
+  while (std::scanf("%lld", &nblk) == 1) {
+    const dim3 g = wh::xcd_grid(nblk);
+    const long long total = (long long)g.x * g.y;
+    std::vector<unsigned char> seen((size_t)nblk, 0);
+    long long dup = 0, missing = 0;
+    for (long long L = 0; L < total; ++L) {
+      const long long lb = wh::xcd_block(L, total);
+      if (lb < nblk && seen[(size_t)lb]++) ++dup;
+    }
+    for (long long b = 0; b < nblk; ++b) missing += !seen[(size_t)b];
+    std::printf("%u %u %lld %lld\n", g.x, g.y, dup, missing);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def xcd(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    d = tmp_path_factory.mktemp("xcd_grid")
+    src, exe = d / "xcd.hip", d / "xcd"
+    src.write_text(XCD_PROGRAM)
+    subprocess.run([hipcc, "-O2", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+                    "-packed-fp32-ops", "-I", os.path.join(ROOT, "paper_2504_03074_amd", "csrc"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+
+    def run(nblks):
+        text = "".join(f"{n}\n" for n in nblks)
+        out = subprocess.run([str(exe)], input=text, capture_output=True, text=True, check=True).stdout
+        return [tuple(int(x) for x in line.split()) for line in out.splitlines()]
+    return run
+
+
+def test_xcd_numbering_covers_every_block_once(xcd):
+    """Every logical block gets exactly one work-group, for one-row grids and
+    for the rows of 2^16 work-groups past 2^24 blocks (the 512^3 first step:
+    9 x 129 x 129 blocks); every row is a multiple of 8 work-groups and at
+    most 2^26 of them (64 work-items each, 2^32 per launch dimension)."""
+    nblks = [1, 7, 8, 9, 1000, 9 * 129 * 129, (1 << 24) - 3, (1 << 24) + 5, 3 * (1 << 24) + 1]
+    for n, (gx, gy, dup, missing) in zip(nblks, xcd(nblks)):
+        assert dup == 0 and missing == 0, n
+        assert gx % 8 == 0 and gx * 64 <= 1 << 32, n
+        assert gx * gy >= n and gx * gy - n < max(8, gx), n
+        assert (gy == 1) == (n <= 1 << 24), n
